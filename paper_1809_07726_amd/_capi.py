@@ -1,0 +1,135 @@
+"""ctypes binding of libgbremd.so (include/gbremd.h).
+
+Argument marshalling only: tensors are checked for device, dtype and
+contiguity and passed as raw device pointers on torch's current stream; every
+step of the computation runs in the library's HIP kernels.  Importing this
+module fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgbremd.so")
+
+GBR_OK, GBR_E_INVAL, GBR_E_HIP, GBR_E_NOMEM, GBR_E_NODEVICE, GBR_E_NUMERIC = 0, -1, -2, -3, -4, -5
+ERR_NONFINITE, ERR_OVERFLOW, ERR_RADIUS, ERR_SITE = 1, 2, 4, 8
+FX_BITS_FORCE, FX_BITS_ENERGY = 40, 32
+GRAD_Q, GRAD_RHO, ZERO_OUT = 1, 2, 4
+MD_INIT_FORCES, MD_GRAPH = 1, 2
+DIM_E, DIM_PH, DIM_T = 0, 1, 2
+K_BORN_PAIR, K_ENERGY_PAIR, K_CHAIN_PAIR, K_PER_ATOM, K_TITRATION, K_EXCHANGE, K_COUNT = range(7)
+KERNEL_KINDS = ("born_pair", "energy_pair", "chain_pair", "per_atom", "titration", "exchange")
+
+EXPORTED = ("gbr_ctx_create", "gbr_ctx_destroy", "gbr_check", "gbr_last_error", "gbr_ctx_sizes",
+            "gbr_set_launch", "gbr_set_blocking", "gbr_set_timing", "gbr_get_timing",
+            "gb_born_radii", "gb_energy_forces", "titration_delta_e", "remd_exchange", "md_step",
+            "gbr_fx_to_float", "gbr_energies", "gbr_exchange_inputs")
+
+
+class GBParams(C.Structure):
+    _fields_ = [("k_e", C.c_double), ("eps_in", C.c_double), ("eps_out", C.c_double),
+                ("offset", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
+                ("gamma", C.c_double)]
+
+
+def obc2() -> GBParams:
+    """OBC-II (igb=2) constants."""
+    return GBParams(332.0522173, 1.0, 78.5, 0.09, 1.0, 0.8, 4.85)
+
+
+_vp = C.c_void_p
+
+
+class Sites(C.Structure):
+    _fields_ = [("n_sites", C.c_int32), ("max_states", C.c_int32),
+                ("rep_site_off", _vp), ("site_off", _vp), ("site_atoms", _vp), ("site_rep", _vp),
+                ("site_type", _vp), ("n_states", _vp), ("state_q", _vp), ("state_nH", _vp),
+                ("state_ne", _vp), ("G_ref", _vp), ("ref_value", _vp)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("n_inst", C.c_int32), ("nE", C.c_int32), ("npH", C.c_int32), ("nT", C.c_int32),
+                ("E_vals", _vp), ("pH_vals", _vp), ("T_vals", _vp),
+                ("n_dims", C.c_int32), ("dim_order", C.c_int32 * 3)]
+
+
+class MDState(C.Structure):
+    _fields_ = [("xyz", _vp), ("v", _vp), ("q", _vp), ("force_fx", _vp), ("energy_fx", _vp),
+                ("R", _vp), ("dRdpsi", _vp), ("site_state", _vp), ("target_idx", _vp),
+                ("grid_rep", _vp), ("ke", _vp), ("mc_stats", _vp), ("ex_stats", _vp)]
+
+
+class MDParams(C.Structure):
+    _fields_ = [("rho", _vp), ("screen", _vp), ("sigma", _vp), ("eps", _vp), ("mass", _vp),
+                ("x0", _vp), ("k_tether", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
+                ("mc_every", C.c_int32), ("ex_every", C.c_int32), ("eps_mode", C.c_int32),
+                ("sites", Sites), ("grid", Grid)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python -m paper_1809_07726_amd.build")
+    L = C.CDLL(LIB_PATH)
+    i32, i64, u64, P = C.c_int32, C.c_int64, C.c_uint64, C.POINTER
+    L.gbr_last_error.restype = C.c_char_p
+    L.gbr_ctx_create.argtypes = [P(_vp), P(GBParams), i32, P(i32)]
+    L.gbr_ctx_destroy.argtypes = [_vp]
+    L.gbr_check.argtypes = [_vp, _vp, P(C.c_uint32)]
+    L.gbr_ctx_sizes.argtypes = [_vp, P(i32), P(i32), P(i64)]
+    L.gbr_set_launch.argtypes = [_vp, i32, i32]
+    L.gbr_set_blocking.argtypes = [_vp, i32, i32, i32]
+    L.gbr_set_timing.argtypes = [_vp, i32]
+    L.gbr_get_timing.argtypes = [_vp, P(C.c_double), P(i64)]
+    L.gb_born_radii.argtypes = [_vp] + [_vp] * 6 + [_vp]
+    L.gb_energy_forces.argtypes = [_vp] + [_vp] * 9 + [_vp, _vp, i32, _vp, _vp, _vp]
+    L.titration_delta_e.argtypes = [_vp, _vp, _vp, _vp, P(Sites), _vp, i32, _vp, _vp]
+    L.remd_exchange.argtypes = [_vp, P(Grid), u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, u64, _vp]
+    L.md_step.argtypes = [_vp, P(MDState), P(MDParams), u64, u64, i32, i32, _vp]
+    L.gbr_fx_to_float.argtypes = [_vp, _vp, i32, i32, _vp, i32, _vp, _vp]
+    L.gbr_energies.argtypes = [_vp, _vp, _vp, _vp]
+    L.gbr_exchange_inputs.argtypes = [_vp, P(MDState), P(MDParams), _vp, _vp, _vp, _vp]
+    for name in EXPORTED:
+        if name != "gbr_last_error":
+            getattr(L, name).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+class GBRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gbremd error {code}: {msg}")
+        self.code = code
+
+
+def check(rc: int):
+    if rc != GBR_OK:
+        raise GBRError(rc, lib.gbr_last_error().decode(errors="replace"))
+
+
+def ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA/HIP tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream

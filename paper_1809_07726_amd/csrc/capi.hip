@@ -1,0 +1,594 @@
+// capi.hip -- the C ABI declared in include/gbremd.h: argument checks,
+// context and workspace, the per-call launch sequences, kernel timing and the
+// captured per-step graphs of md_step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gbr_internal.h"
+
+using namespace gbr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(GBR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define GBR_HIP(call)                                          \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);      \
+    } while (0)
+
+template <typename T>
+int dev_alloc(T** p, size_t n) {
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+    if (e != hipSuccess) return fail(GBR_E_NOMEM, "hipMalloc(%zu bytes): %s", n * sizeof(T),
+                                     hipGetErrorString(e));
+    return GBR_OK;
+}
+
+// Timing: a pair of events around each timed launch when enabled.
+struct Timed {
+    gbr_ctx* c;
+    int kind;
+    hipStream_t s;
+    hipEvent_t stop = nullptr;
+    Timed(gbr_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
+        Timer& t = c->timer;
+        if (!t.enabled) return;
+        if (t.used + 2 > t.pool.size()) {
+            size_t old = t.pool.size();
+            t.pool.resize(old + 512);
+            for (size_t i = old; i < t.pool.size(); ++i)
+                if (hipEventCreate(&t.pool[i]) != hipSuccess) t.pool[i] = nullptr;
+        }
+        hipEvent_t start = t.pool[t.used];
+        stop = t.pool[t.used + 1];
+        if (!start || !stop) { stop = nullptr; return; }
+        t.kind.push_back(kind);
+        t.used += 2;
+        (void)hipEventRecord(start, s);
+    }
+    ~Timed() {
+        if (stop) (void)hipEventRecord(stop, s);
+    }
+};
+
+int check_ctx(const gbr_ctx* c) {
+    if (!c) return fail(GBR_E_INVAL, "null context");
+    return GBR_OK;
+}
+
+#define REQ(p) \
+    do { if (!(p)) return fail(GBR_E_INVAL, "%s: required pointer %s is null", __func__, #p); } while (0)
+
+int check_sites(const gbr_ctx* c, const gbr_sites& s) {
+    if (s.n_sites < 0) return fail(GBR_E_INVAL, "n_sites < 0");
+    if (s.n_sites == 0) return GBR_OK;
+    if (s.max_states < 2 || s.max_states > 8) return fail(GBR_E_INVAL, "max_states must be 2..8");
+    if (!s.rep_site_off || !s.site_off || !s.site_atoms || !s.site_rep || !s.site_type ||
+        !s.n_states || !s.state_q || !s.state_nH || !s.state_ne || !s.G_ref || !s.ref_value)
+        return fail(GBR_E_INVAL, "gbr_sites: a table pointer is null");
+    (void)c;
+    return GBR_OK;
+}
+
+int check_grid(const gbr_ctx* c, const gbr_grid& g) {
+    if (g.n_inst < 1 || g.nE < 1 || g.npH < 1 || g.nT < 1)
+        return fail(GBR_E_INVAL, "grid sizes must be >= 1");
+    if ((int64_t)g.n_inst * g.nE * g.npH * g.nT != c->n_rep)
+        return fail(GBR_E_INVAL, "grid n_inst*nE*npH*nT (%lld) != n_rep (%d)",
+                    (long long)g.n_inst * g.nE * g.npH * g.nT, c->n_rep);
+    if (!g.E_vals || !g.pH_vals || !g.T_vals) return fail(GBR_E_INVAL, "grid value table is null");
+    if (g.n_dims < 1 || g.n_dims > 3) return fail(GBR_E_INVAL, "n_dims must be 1..3");
+    for (int k = 0; k < g.n_dims; ++k)
+        if (g.dim_order[k] < 0 || g.dim_order[k] > 2) return fail(GBR_E_INVAL, "bad dim_order");
+    return GBR_OK;
+}
+
+void build_pair_list(const std::vector<int32_t>& off, int ni, std::vector<int2>& out) {
+    out.clear();
+    const int n_rep = (int)off.size() - 1;
+    for (int r = 0; r < n_rep; ++r) {
+        const int n = off[r + 1] - off[r];
+        const int T = (n + 63) / 64;
+        const int B = (n + 64 * ni - 1) / (64 * ni);
+        for (int ib = 0; ib < B; ++ib)
+            for (int j = ib * ni; j < T; ++j) out.push_back(make_int2(r, (ib << 16) | j));
+    }
+}
+
+int upload(void* dst, const void* src, size_t bytes) {
+    GBR_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return GBR_OK;
+}
+
+// One force evaluation inside md_step (the caller has cleared the accumulators).
+int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, hipStream_t s) {
+    hipError_t e;
+    {
+        Timed t(c, GBR_K_BORN_PAIR, s);
+        e = launch_born_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "born pair");
+    {
+        Timed t(c, GBR_K_PER_ATOM, s);
+        e = launch_born_finalize(c, a.pr.rho, a.st.R, a.st.dRdpsi, nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "born finalize");
+    if (with_mc) {
+        Timed t(c, GBR_K_TITRATION, s);
+        e = launch_mc(c, a, s);
+        if (e != hipSuccess) return hip_fail(e, "mc");
+    }
+    {
+        Timed t(c, GBR_K_ENERGY_PAIR, s);
+        e = launch_energy_pair(c, a.st.xyz, a.st.q, a.st.R, a.pr.sigma, a.pr.eps, a.st.force_fx,
+                               a.st.energy_fx, nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "energy pair");
+    {
+        Timed t(c, GBR_K_PER_ATOM, s);
+        e = launch_coef(c, a.st.q, a.pr.rho, a.st.R, a.st.dRdpsi, a.st.energy_fx, nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "coef");
+    {
+        Timed t(c, GBR_K_CHAIN_PAIR, s);
+        e = launch_chain_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, a.st.force_fx, nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "chain pair");
+    return GBR_OK;
+}
+
+// The launches of one MD step (kind bit 0: MC attempts, bit 1: exchange attempt).
+int md_one_step(gbr_ctx* c, const MDArgs& a, int kind, hipStream_t s) {
+    hipError_t e = launch_step_begin(c, s);
+    if (e != hipSuccess) return hip_fail(e, "step begin");
+    {
+        Timed t(c, GBR_K_PER_ATOM, s);
+        e = launch_md_first(c, a, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "md first");
+    int rc = md_forces(c, a, (kind & 1) != 0, s);
+    if (rc) return rc;
+    {
+        Timed t(c, GBR_K_PER_ATOM, s);
+        e = launch_md_last(c, a, 1, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "md last");
+    if (kind & 2) {
+        Timed t(c, GBR_K_EXCHANGE, s);
+        e = launch_exchange_inputs(c, a.st, a.pr, c->ex_nH, c->ex_ne, c->ex_eps, s);
+        if (e == hipSuccess)
+            e = launch_exchange(c, a.pr.grid, 0, c->step, a.pr.ex_every, c->ex_nH, c->ex_ne,
+                                c->ex_eps, a.st.target_idx, a.st.grid_rep, c->ex_vscale,
+                                a.st.ex_stats, a.seed, s);
+        if (e == hipSuccess) e = launch_apply_vscale(c, c->ex_vscale, a.st.v, s);
+        if (e != hipSuccess) return hip_fail(e, "exchange");
+    }
+    return GBR_OK;
+}
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    template <typename T> void add(const T& v) {
+        const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+        for (size_t i = 0; i < sizeof(T); ++i) { h ^= p[i]; h *= 1099511628211ull; }
+    }
+};
+
+// Key of a captured step graph: every pointer and scalar the step's kernels take
+// (field by field, so struct padding never enters the key).
+uint64_t hash_args(const MDArgs& a) {
+    Fnv f;
+    const gbr_md_state& s = a.st;
+    const gbr_md_params& p = a.pr;
+    f.add(s.xyz); f.add(s.v); f.add(s.q); f.add(s.force_fx); f.add(s.energy_fx); f.add(s.R);
+    f.add(s.dRdpsi); f.add(s.site_state); f.add(s.target_idx); f.add(s.grid_rep); f.add(s.ke);
+    f.add(s.mc_stats); f.add(s.ex_stats);
+    f.add(p.rho); f.add(p.screen); f.add(p.sigma); f.add(p.eps); f.add(p.mass); f.add(p.x0);
+    f.add(p.k_tether); f.add(p.dt); f.add(p.gamma); f.add(p.mc_every); f.add(p.ex_every);
+    f.add(p.eps_mode);
+    const gbr_sites& t = p.sites;
+    f.add(t.n_sites); f.add(t.max_states); f.add(t.rep_site_off); f.add(t.site_off);
+    f.add(t.site_atoms); f.add(t.site_rep); f.add(t.site_type); f.add(t.n_states); f.add(t.state_q);
+    f.add(t.state_nH); f.add(t.state_ne); f.add(t.G_ref); f.add(t.ref_value);
+    const gbr_grid& g = p.grid;
+    f.add(g.n_inst); f.add(g.nE); f.add(g.npH); f.add(g.nT); f.add(g.E_vals); f.add(g.pH_vals);
+    f.add(g.T_vals); f.add(g.n_dims); f.add(g.dim_order[0]); f.add(g.dim_order[1]);
+    f.add(g.dim_order[2]);
+    f.add(a.seed);
+    return f.h | 1ull;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gbr_last_error(void) { return g_last_error.c_str(); }
+
+int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
+                   const int32_t* atom_off_host) {
+    if (!out) return fail(GBR_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!params) return fail(GBR_E_INVAL, "params is null");
+    if (n_rep < 1) return fail(GBR_E_INVAL, "n_rep must be >= 1");
+    if (!atom_off_host) return fail(GBR_E_INVAL, "atom_off_host is null");
+    if (atom_off_host[0] != 0) return fail(GBR_E_INVAL, "atom_off[0] must be 0");
+    int64_t pairs = 0;
+    int32_t max_n = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const int n = atom_off_host[r + 1] - atom_off_host[r];
+        if (n < 1) return fail(GBR_E_INVAL, "replica %d has %d atoms", r, n);
+        if (n > 64 * 65535) return fail(GBR_E_INVAL, "replica %d too large", r);
+        max_n = std::max(max_n, n);
+        pairs += (int64_t)n * (n - 1) / 2;
+    }
+    const gbr_gb_params& p = *params;
+    if (!(p.k_e > 0) || !(p.eps_in > 0) || !(p.eps_out > 0) || !(p.offset >= 0))
+        return fail(GBR_E_INVAL, "GB parameters out of range");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(GBR_E_NODEVICE, "no HIP device");
+    int dev = 0;
+    GBR_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    GBR_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GBR_E_NODEVICE, "device %d is %s; this library is built for gfx950", dev,
+                    prop.gcnArchName);
+
+    gbr_ctx* c = new gbr_ctx();
+    c->device = dev;
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->prm = p;
+    c->n_rep = n_rep;
+    c->n_atoms = atom_off_host[n_rep];
+    c->max_n = max_n;
+    c->n_pairs = pairs;
+    c->h_atom_off.assign(atom_off_host, atom_off_host + n_rep + 1);
+    const int N = c->n_atoms;
+    int rc = GBR_OK;
+    auto done = [&](int code) { if (code) { gbr_ctx_destroy(c); } return code; };
+    if ((rc = dev_alloc(&c->atom_off, n_rep + 1))) return done(rc);
+    if ((rc = upload(c->atom_off, atom_off_host, sizeof(int32_t) * (n_rep + 1)))) return done(rc);
+    std::vector<int2> tl;
+    for (int r = 0; r < n_rep; ++r) {
+        const int n = atom_off_host[r + 1] - atom_off_host[r];
+        for (int t = 0; t < (n + 63) / 64; ++t) tl.push_back(make_int2(r, t));
+    }
+    c->n_tiles = (int32_t)tl.size();
+    if ((rc = dev_alloc(&c->tiles, tl.size()))) return done(rc);
+    if ((rc = upload(c->tiles, tl.data(), sizeof(int2) * tl.size()))) return done(rc);
+    const int nis[4] = {1, 2, 4, 8};
+    std::vector<int2> items;
+    for (int k = 0; k < 4; ++k) {
+        build_pair_list(c->h_atom_off, nis[k], items);
+        if (items.size() > 0x7FFFFFFF) return done(fail(GBR_E_INVAL, "work list too long"));
+        c->lists[k].ni = nis[k];
+        c->lists[k].n_items = (int32_t)items.size();
+        if ((rc = dev_alloc(&c->lists[k].items, items.size()))) return done(rc);
+        if (!items.empty() &&
+            (rc = upload(c->lists[k].items, items.data(), sizeof(int2) * items.size())))
+            return done(rc);
+    }
+    // default register blocking: more i atoms per lane for larger replicas
+    const int ni = max_n >= 4096 ? 8 : (max_n >= 512 ? 4 : (max_n >= 128 ? 2 : 1));
+    c->ni_born = c->ni_energy = c->ni_chain = ni;
+    if ((rc = dev_alloc(&c->psi_fx, N))) return done(rc);
+    if ((rc = dev_alloc(&c->dEdR_fx, N))) return done(rc);
+    if ((rc = dev_alloc(&c->dEdR, N))) return done(rc);
+    if ((rc = dev_alloc(&c->chain_c, N))) return done(rc);
+    if ((rc = dev_alloc(&c->ke_fx, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->ex_nH, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->ex_ne, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->ex_eps, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->ex_vscale, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->step, 2))) return done(rc);
+    if ((rc = dev_alloc(&c->err, 1))) return done(rc);
+    hipError_t e = hipMemset(c->err, 0, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(c->step, 0, 2 * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return done(hip_fail(e, "context init"));
+    *out = c;
+    return GBR_OK;
+}
+
+int gbr_ctx_destroy(gbr_ctx* c) {
+    if (!c) return GBR_OK;
+    (void)hipDeviceSynchronize();
+    for (auto& g : c->graph) if (g) (void)hipGraphExecDestroy(g);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (auto& ev : c->timer.pool) if (ev) (void)hipEventDestroy(ev);
+    (void)hipFree(c->atom_off);
+    (void)hipFree(c->tiles);
+    for (auto& L : c->lists) (void)hipFree(L.items);
+    (void)hipFree(c->psi_fx); (void)hipFree(c->dEdR_fx); (void)hipFree(c->dEdR); (void)hipFree(c->chain_c);
+    (void)hipFree(c->ke_fx); (void)hipFree(c->ex_nH); (void)hipFree(c->ex_ne); (void)hipFree(c->ex_eps);
+    (void)hipFree(c->ex_vscale); (void)hipFree(c->step); (void)hipFree(c->err);
+    delete c;
+    return GBR_OK;
+}
+
+int gbr_ctx_sizes(const gbr_ctx* c, int32_t* n_atoms, int32_t* n_rep, int64_t* n_pairs) {
+    if (int rc = check_ctx(c)) return rc;
+    if (n_atoms) *n_atoms = c->n_atoms;
+    if (n_rep) *n_rep = c->n_rep;
+    if (n_pairs) *n_pairs = c->n_pairs;
+    return GBR_OK;
+}
+
+int gbr_set_launch(gbr_ctx* c, int32_t waves_per_group, int32_t groups_per_cu) {
+    if (int rc = check_ctx(c)) return rc;
+    if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
+        return fail(GBR_E_INVAL, "waves_per_group must be 1, 2 or 4");
+    if (groups_per_cu < 1 || groups_per_cu > 32) return fail(GBR_E_INVAL, "groups_per_cu 1..32");
+    c->shape.waves_per_group = waves_per_group;
+    c->shape.groups_per_cu = groups_per_cu;
+    return GBR_OK;
+}
+
+int gbr_set_blocking(gbr_ctx* c, int32_t ni_born, int32_t ni_energy, int32_t ni_chain) {
+    if (int rc = check_ctx(c)) return rc;
+    auto ok = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
+    if (!ok(ni_born) || !ok(ni_energy) || !ok(ni_chain))
+        return fail(GBR_E_INVAL, "i atoms per lane must be 1, 2, 4 or 8");
+    c->ni_born = ni_born; c->ni_energy = ni_energy; c->ni_chain = ni_chain;
+    for (auto& g : c->graph) if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    return GBR_OK;
+}
+
+int gbr_set_timing(gbr_ctx* c, int32_t enable) {
+    if (int rc = check_ctx(c)) return rc;
+    c->timer.enabled = enable != 0;
+    return GBR_OK;
+}
+
+int gbr_get_timing(gbr_ctx* c, double* ms_out, int64_t* count_out) {
+    if (int rc = check_ctx(c)) return rc;
+    Timer& t = c->timer;
+    for (size_t i = 0; i + 1 < t.used; i += 2) {
+        GBR_HIP(hipEventSynchronize(t.pool[i + 1]));
+        float ms = 0.0f;
+        GBR_HIP(hipEventElapsedTime(&ms, t.pool[i], t.pool[i + 1]));
+        const int k = t.kind[i / 2];
+        t.ms[k] += ms;
+        t.count[k] += 1;
+    }
+    for (int k = 0; k < GBR_K_COUNT; ++k) {
+        if (ms_out) ms_out[k] = t.ms[k];
+        if (count_out) count_out[k] = t.count[k];
+        t.ms[k] = 0.0;
+        t.count[k] = 0;
+    }
+    t.used = 0;
+    t.kind.clear();
+    return GBR_OK;
+}
+
+int gbr_check(gbr_ctx* c, hipStream_t stream, uint32_t* bits_out) {
+    if (int rc = check_ctx(c)) return rc;
+    GBR_HIP(hipStreamSynchronize(stream));
+    uint32_t bits = 0;
+    GBR_HIP(hipMemcpy(&bits, c->err, sizeof(bits), hipMemcpyDeviceToHost));
+    GBR_HIP(hipMemset(c->err, 0, sizeof(uint32_t)));
+    GBR_HIP(hipDeviceSynchronize());
+    if (bits_out) *bits_out = bits;
+    if (bits) return fail(GBR_E_NUMERIC, "device error word 0x%x", bits);
+    return GBR_OK;
+}
+
+int gb_born_radii(gbr_ctx* c, const float* xyz, const float* rho, const float* screen, float* R,
+                  float* dRdpsi, double* psi, hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(xyz); REQ(rho); REQ(screen); REQ(R); REQ(dRdpsi);
+    hipError_t e = launch_zero_i64(c->psi_fx, c->n_atoms, s);
+    if (e != hipSuccess) return hip_fail(e, "zero");
+    {
+        Timed t(c, GBR_K_BORN_PAIR, s);
+        e = launch_born_pair(c, xyz, rho, screen, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "born pair");
+    {
+        Timed t(c, GBR_K_PER_ATOM, s);
+        e = launch_born_finalize(c, rho, R, dRdpsi, psi, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "born finalize");
+    return GBR_OK;
+}
+
+int gb_energy_forces(gbr_ctx* c, const float* xyz, const float* q, const float* rho,
+                     const float* screen, const float* sigma, const float* eps, const float* R,
+                     const float* dRdpsi, const double* psi, int64_t* force_fx,
+                     int64_t* energy_fx, int32_t flags, int64_t* dEdq_fx, int64_t* dEdrho_fx,
+                     hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(xyz); REQ(q); REQ(rho); REQ(screen); REQ(sigma); REQ(eps); REQ(R); REQ(dRdpsi);
+    REQ(force_fx); REQ(energy_fx);
+    if (flags & ~(GBR_GRAD_Q | GBR_GRAD_RHO | GBR_ZERO_OUT))
+        return fail(GBR_E_INVAL, "unknown flag bits 0x%x", flags);
+    const bool gq = flags & GBR_GRAD_Q, gr = flags & GBR_GRAD_RHO;
+    if (gq) REQ(dEdq_fx);
+    if (gr) { REQ(dEdrho_fx); REQ(psi); }
+    const int N = c->n_atoms;
+    hipError_t e = hipSuccess;
+    if (flags & GBR_ZERO_OUT) {
+        e = launch_zero_i64(force_fx, 3ll * N, s);
+        if (e == hipSuccess) e = launch_zero_i64(energy_fx, 4ll * c->n_rep, s);
+        if (e == hipSuccess && gq) e = launch_zero_i64(dEdq_fx, N, s);
+        if (e == hipSuccess && gr) e = launch_zero_i64(dEdrho_fx, N, s);
+    }
+    if (e == hipSuccess) e = launch_zero_i64(c->dEdR_fx, N, s);
+    if (e != hipSuccess) return hip_fail(e, "zero");
+    {
+        Timed t(c, GBR_K_ENERGY_PAIR, s);
+        e = launch_energy_pair(c, xyz, q, R, sigma, eps, force_fx, energy_fx, gq ? dEdq_fx : nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "energy pair");
+    {
+        Timed t(c, GBR_K_PER_ATOM, s);
+        e = launch_coef(c, q, rho, R, dRdpsi, energy_fx, gq ? dEdq_fx : nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "coef");
+    {
+        Timed t(c, GBR_K_CHAIN_PAIR, s);
+        e = launch_chain_pair(c, xyz, rho, screen, force_fx, gr ? dEdrho_fx : nullptr, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "chain pair");
+    if (gr) {
+        Timed t(c, GBR_K_PER_ATOM, s);
+        e = launch_rho_finalize(c, rho, R, dRdpsi, psi, dEdrho_fx, s);
+        if (e != hipSuccess) return hip_fail(e, "rho finalize");
+    }
+    return GBR_OK;
+}
+
+int titration_delta_e(gbr_ctx* c, const float* xyz, const float* q, const float* R,
+                      const gbr_sites* sites, const int32_t* cand, int32_t n_cand, double* dE,
+                      hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(xyz); REQ(q); REQ(R); REQ(sites);
+    if (n_cand < 0) return fail(GBR_E_INVAL, "n_cand < 0");
+    if (n_cand == 0) return GBR_OK;
+    REQ(cand); REQ(dE);
+    if (int rc = check_sites(c, *sites)) return rc;
+    if (sites->n_sites == 0) return fail(GBR_E_INVAL, "no sites");
+    hipError_t e;
+    {
+        Timed t(c, GBR_K_TITRATION, s);
+        e = launch_titration(c, xyz, q, R, *sites, cand, n_cand, dE, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "titration");
+    return GBR_OK;
+}
+
+int remd_exchange(gbr_ctx* c, const gbr_grid* grid, uint64_t attempt, const int32_t* nH,
+                  const int32_t* ne, const double* epsT, int32_t* target_idx, int32_t* grid_rep,
+                  float* vscale, uint32_t* ex_stats, uint64_t seed, hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(grid); REQ(nH); REQ(ne); REQ(epsT); REQ(target_idx); REQ(grid_rep); REQ(vscale);
+    if (int rc = check_grid(c, *grid)) return rc;
+    hipError_t e;
+    {
+        Timed t(c, GBR_K_EXCHANGE, s);
+        e = launch_exchange(c, *grid, attempt, nullptr, 1, nH, ne, epsT, target_idx, grid_rep,
+                            vscale, ex_stats, seed, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "exchange");
+    return GBR_OK;
+}
+
+int gbr_exchange_inputs(gbr_ctx* c, const gbr_md_state* st, const gbr_md_params* pr, int32_t* nH,
+                        int32_t* ne, double* epsT, hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(st); REQ(pr); REQ(nH); REQ(ne); REQ(epsT);
+    REQ(st->site_state); REQ(st->target_idx); REQ(st->energy_fx);
+    if (int rc = check_sites(c, pr->sites)) return rc;
+    if (int rc = check_grid(c, pr->grid)) return rc;
+    hipError_t e = launch_exchange_inputs(c, *st, *pr, nH, ne, epsT, s);
+    if (e != hipSuccess) return hip_fail(e, "exchange inputs");
+    return GBR_OK;
+}
+
+int gbr_fx_to_float(gbr_ctx* c, const int64_t* src, int32_t components, int32_t bits,
+                    const double* scale, int32_t sign, float* dst, hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(src); REQ(dst);
+    if (components < 1 || components > 3) return fail(GBR_E_INVAL, "components must be 1..3");
+    if (bits < 0 || bits > 62) return fail(GBR_E_INVAL, "bits must be 0..62");
+    if (sign != 1 && sign != -1) return fail(GBR_E_INVAL, "sign must be +1 or -1");
+    hipError_t e = launch_fx_to_float(c, src, components, bits, scale, sign, dst, s);
+    if (e != hipSuccess) return hip_fail(e, "fx to float");
+    return GBR_OK;
+}
+
+int gbr_energies(gbr_ctx* c, const int64_t* energy_fx, double* out, hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(energy_fx); REQ(out);
+    hipError_t e = launch_energies(c, energy_fx, out, s);
+    if (e != hipSuccess) return hip_fail(e, "energies");
+    return GBR_OK;
+}
+
+int md_step(gbr_ctx* c, gbr_md_state* st, const gbr_md_params* pr, uint64_t seed, uint64_t step0,
+            int32_t n_steps, int32_t flags, hipStream_t s) {
+    if (int rc = check_ctx(c)) return rc;
+    REQ(st); REQ(pr);
+    REQ(st->xyz); REQ(st->v); REQ(st->q); REQ(st->force_fx); REQ(st->energy_fx); REQ(st->R);
+    REQ(st->dRdpsi); REQ(st->target_idx); REQ(st->grid_rep);
+    REQ(pr->rho); REQ(pr->screen); REQ(pr->sigma); REQ(pr->eps); REQ(pr->mass); REQ(pr->x0);
+    if (n_steps < 0) return fail(GBR_E_INVAL, "n_steps < 0");
+    if (flags & ~(GBR_MD_INIT_FORCES | GBR_MD_GRAPH)) return fail(GBR_E_INVAL, "unknown md flags");
+    if (!(pr->dt >= 0) || !(pr->gamma >= 0)) return fail(GBR_E_INVAL, "dt and gamma must be >= 0");
+    if (pr->mc_every < 0 || pr->ex_every < 0) return fail(GBR_E_INVAL, "intervals must be >= 0");
+    if (int rc = check_grid(c, pr->grid)) return rc;
+    if (int rc = check_sites(c, pr->sites)) return rc;
+    if (pr->mc_every > 0 && pr->sites.n_sites > 0) REQ(st->site_state);
+    if (pr->ex_every > 0 && pr->sites.n_sites > 0) REQ(st->site_state);
+    if (pr->sites.n_sites == 0 && pr->mc_every > 0)
+        return fail(GBR_E_INVAL, "mc_every > 0 needs titratable sites");
+    MDArgs a{*st, *pr, seed};
+    hipError_t e = launch_set_step(c, step0, s);
+    if (e != hipSuccess) return hip_fail(e, "set step");
+    if (flags & GBR_MD_INIT_FORCES) {
+        e = launch_zero_i64(st->force_fx, 3ll * c->n_atoms, s);
+        if (e == hipSuccess) e = launch_zero_i64(st->energy_fx, 4ll * c->n_rep, s);
+        if (e == hipSuccess) e = launch_zero_i64(c->psi_fx, c->n_atoms, s);
+        if (e == hipSuccess) e = launch_zero_i64(c->dEdR_fx, c->n_atoms, s);
+        if (e == hipSuccess) e = launch_zero_i64(c->ke_fx, c->n_rep, s);
+        if (e != hipSuccess) return hip_fail(e, "zero");
+        if (int rc = md_forces(c, a, false, s)) return rc;
+        e = launch_md_last(c, a, 0, s);
+        if (e != hipSuccess) return hip_fail(e, "md init");
+    }
+    const bool use_graph = (flags & GBR_MD_GRAPH) != 0 && !c->timer.enabled;
+    uint64_t key = use_graph ? hash_args(a) : 0;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        const uint64_t n = step0 + (uint64_t)k;
+        int kind = 0;
+        if (pr->mc_every > 0 && (n + 1) % (uint64_t)pr->mc_every == 0) kind |= 1;
+        if (pr->ex_every > 0 && (n + 1) % (uint64_t)pr->ex_every == 0) kind |= 2;
+        if (!use_graph) {
+            if (int rc = md_one_step(c, a, kind, s)) return rc;
+            continue;
+        }
+        if (!c->graph[kind] || c->graph_key[kind] != key) {
+            if (c->graph[kind]) { (void)hipGraphExecDestroy(c->graph[kind]); c->graph[kind] = nullptr; }
+            if (!c->cap_stream) GBR_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            GBR_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = md_one_step(c, a, kind, c->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+            if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+            if (ec != hipSuccess) return hip_fail(ec, "end capture");
+            hipError_t ei = hipGraphInstantiate(&c->graph[kind], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) return hip_fail(ei, "graph instantiate");
+            c->graph_key[kind] = key;
+        }
+        GBR_HIP(hipGraphLaunch(c->graph[kind], s));
+    }
+    return GBR_OK;
+}
+
+}  // extern "C"

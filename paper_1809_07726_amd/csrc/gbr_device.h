@@ -1,0 +1,254 @@
+// gbr_device.h -- device helpers shared by the library's kernels:
+// fixed-point accumulation, wavefront reductions, the counter-based RNG, and
+// the FP32 descreening term with its derivatives.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gbremd.h"
+#include "hct_poly.h"
+
+#define GBR_WAVE 64
+#define GBR_TILE 64          // atoms per pair tile (one per lane)
+
+namespace gbr {
+
+// ---------------------------------------------------------------- constants
+constexpr double KB = 0.001987204259;     // kcal/(mol K), CODATA 2018 R / 4184 J/kcal
+constexpr double FARADAY = 23.0605480;    // kcal/(mol V), CODATA 2018 F / 4184 J/kcal
+constexpr double LN10 = 2.302585092994045684;
+constexpr double ACC_CONV = 418.4;        // 1 kcal/(mol A amu) in A/ps^2
+constexpr double FX_FORCE = 1099511627776.0;   // 2^40
+constexpr double FX_ENERGY = 4294967296.0;     // 2^32
+constexpr double INV_FX_FORCE = 1.0 / FX_FORCE;
+constexpr double INV_FX_ENERGY = 1.0 / FX_ENERGY;
+
+enum Stream : uint32_t { STREAM_O = 1, STREAM_MCPH = 2, STREAM_MCRED = 3, STREAM_EX = 4 };
+
+// Per-launch constants of the GB model (FP32 copies for the pair kernels).
+struct GBConst {
+    float ke;        // k_e
+    float ke_in;     // k_e / eps_in
+    float tau;       // 1/eps_in - 1/eps_out
+    float offset;    // dielectric offset
+    double ke_d, ke_in_d, tau_d, offset_d, alpha, beta, gamma;
+};
+
+// ------------------------------------------------------------ fixed point
+__device__ __forceinline__ void raise_error(uint32_t* err, uint32_t bits) {
+    __hip_atomic_fetch_or(err, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// round(v * scale) with saturation reported in the error word.
+__device__ __forceinline__ long long to_fixed(double v, double scale, uint32_t* err) {
+    double s = v * scale;
+    if (!(fabs(s) < 4.6116860184273879e18)) {   // 2^62
+        raise_error(err, (v == v && fabs(v) <= 1.7976931348623157e308) ? GBR_ERR_OVERFLOW
+                                                                        : GBR_ERR_NONFINITE);
+        return 0;
+    }
+    return (long long)__builtin_rint(s);
+}
+
+__device__ __forceinline__ void atomic_add_fx(int64_t* p, long long v) {
+    if (v != 0)
+        __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(p),
+                               static_cast<unsigned long long>(v), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double from_fixed(int64_t v, double inv_scale) {
+    return (double)v * inv_scale;
+}
+
+// -------------------------------------------------------- wave reductions
+// DPP-based sum over the 64 lanes of a wavefront; the total is valid in lane 63.
+// Every lane must be active.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                  CTRL, ROW_MASK, 0xF, true));
+}
+
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+    v += dpp_f<0xB1>(v);        // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);        // quad_perm [2,3,0,1]
+    v += dpp_f<0x124>(v);       // row_ror:4
+    v += dpp_f<0x128>(v);       // row_ror:8  -> every lane holds its row's sum
+    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v = wave_sum_to_63(v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+    // doubles: butterfly through shuffles (used only once per tile)
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, GBR_WAVE);
+    return v;
+}
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// -------------------------------------------------- Philox4x32-10 (SC'11)
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// draw for (sub, entity, step, stream) keyed by seed
+__device__ __forceinline__ U4 draw(uint64_t seed, uint32_t sub, uint32_t entity, uint64_t step,
+                                   uint32_t stream) {
+    return philox(sub, entity, (uint32_t)step,
+                  (stream << 24) | (uint32_t)((step >> 32) & 0xFFFFFFu),
+                  (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ uint32_t choose(uint32_t w, uint32_t n) {
+    return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+__device__ __forceinline__ void normal2(U4 w, double& n0, double& n1) {
+    double u1 = uniform53(w.x, w.y), u2 = uniform53(w.z, w.w);
+    double rad = sqrt(-2.0 * log(1.0 - u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    n0 = rad * cs;
+    n1 = rad * sn;
+}
+
+// ---------------------------------------------- descreening term (FP32)
+// h(r; rt, s) for a sphere of radius s at distance r from an atom of offset
+// radius rt: twice the integral over shells t >= rt of (covered fraction)/t^2.
+//  - sphere inside the atom (r + s <= rt): 0
+//  - distant sphere (r - s >= rt, s/r <= HCT_FAR_XMAX): (x^3/r) G(x^2), x = s/r
+//  - otherwise the closed form with L = max(rt, |r - s|), U = r + s, plus the
+//    engulfing term when rt < s - r.
+__device__ __forceinline__ float poly_G(float y) {
+    float p = hct_G_coef[HCT_G_DEG];
+#pragma unroll
+    for (int k = HCT_G_DEG - 1; k >= 0; --k) p = __builtin_fmaf(p, y, hct_G_coef[k]);
+    return p;
+}
+__device__ __forceinline__ float poly_Q(float y) {
+    float p = hct_Q_coef[HCT_Q_DEG];
+#pragma unroll
+    for (int k = HCT_Q_DEG - 1; k >= 0; --k) p = __builtin_fmaf(p, y, hct_Q_coef[k]);
+    return p;
+}
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// natural log through the hardware log2
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ __forceinline__ float fexp_neg(float x) { return __builtin_amdgcn_exp2f(-x * 1.4426950408889634f); }
+
+struct HctNear {
+    float L, U, iL, iU;
+    bool engulfed;
+};
+
+__device__ __forceinline__ float hct_closed(float r, float rinv, float rt, float s) {
+    float U = r + s;
+    float rms = r - s;
+    float L = fmaxf(rt, fabsf(rms));
+    float iL = frcp(L), iU = frcp(U);
+    float h = (iL - iU) + (iU * iU - iL * iL) * ((r * r - s * s) * 0.25f * rinv)
+            + 0.5f * rinv * flog(L * iU);
+    if (rt < -rms) h += 2.0f * (frcp(rt) - iL);
+    return h;
+}
+
+__device__ __forceinline__ float hct_h(float r, float rinv, float rt, float s) {
+    float x = s * rinv;
+    float y = x * x;
+    float h = x * y * rinv * poly_G(y);
+    bool far = (r - s >= rt) && (x <= HCT_FAR_XMAX);
+    if (!far) {
+        h = (r + s <= rt) ? 0.0f : hct_closed(r, rinv, rt, s);
+    }
+    return h;
+}
+
+// dh/dr.  Distant sphere: -(x^3/r^2) Q(x^2).  Otherwise
+//   dh/dr = [ (r^2 + s^2)(1/U^2 - 1/L^2)/2 + ln(U/L) ] / (2 r^2)
+// (the boundary terms of the shell integral vanish or cancel in every branch).
+__device__ __forceinline__ float hct_dr_closed(float r, float rinv, float rt, float s) {
+    float U = r + s;
+    float L = fmaxf(rt, fabsf(r - s));
+    float iL = frcp(L), iU = frcp(U);
+    float a = (r * r + s * s) * (iU * iU - iL * iL) * 0.5f - flog(L * iU);
+    return a * 0.5f * rinv * rinv;
+}
+
+__device__ __forceinline__ float hct_dr(float r, float rinv, float rt, float s) {
+    float x = s * rinv;
+    float y = x * x;
+    float d = -(x * y * rinv * rinv) * poly_Q(y);
+    bool far = (r - s >= rt) && (x <= HCT_FAR_XMAX);
+    if (!far) {
+        d = (r + s <= rt) ? 0.0f : hct_dr_closed(r, rinv, rt, s);
+    }
+    return d;
+}
+
+// All three partials (for the radius adjoint).
+//   dh/drt: overlap (L = rt): ((r - rt)^2 - s^2) / (2 r rt^3); engulfed: -2/rt^2; else 0
+//   dh/ds : (s / (2r)) (1/L^2 - 1/U^2); distant sphere: 2 s^2 / (r^2 - s^2)^2
+__device__ __forceinline__ void hct_grad3(float r, float rinv, float rt, float s,
+                                          float& d_r, float& d_rt, float& d_s) {
+    float x = s * rinv;
+    float y = x * x;
+    bool far = (r - s >= rt) && (x <= HCT_FAR_XMAX);
+    if (far) {
+        d_r = -(x * y * rinv * rinv) * poly_Q(y);
+        d_rt = 0.0f;
+        float lu = (r - s) * (r + s);
+        float ilu = frcp(lu);
+        d_s = 2.0f * s * s * ilu * ilu;
+    } else if (r + s <= rt) {
+        d_r = 0.0f; d_rt = 0.0f; d_s = 0.0f;
+    } else {
+        float U = r + s;
+        float rms = r - s;
+        bool at_rt = rt >= fabsf(rms);
+        float L = at_rt ? rt : fabsf(rms);
+        float iL = frcp(L), iU = frcp(U);
+        float dd = iL * iL - iU * iU;
+        d_r = ((r * r + s * s) * (-dd) * 0.5f - flog(L * iU)) * 0.5f * rinv * rinv;
+        d_s = 0.5f * s * rinv * dd;
+        float irt = frcp(rt);
+        if (at_rt) {
+            float t = r - rt;
+            d_rt = (t * t - s * s) * 0.5f * rinv * irt * irt * irt;
+        } else if (rt < -rms) {
+            d_rt = -2.0f * irt * irt;
+        } else {
+            d_rt = 0.0f;
+        }
+    }
+}
+
+}  // namespace gbr

@@ -1,0 +1,126 @@
+// gbr_internal.h -- host-side declarations shared by the library's
+// translation units: the context layout and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "gbremd.h"
+
+namespace gbr {
+
+// Pair work item: replica, I-block (NI*64 atoms) and J-tile (64 atoms).
+struct PairList {
+    int ni = 0;                // i atoms per lane the list was built for
+    int2* items = nullptr;     // {rep, (IB << 16) | J}
+    int32_t n_items = 0;
+};
+
+struct LaunchShape {
+    int waves_per_group = 4;
+    int groups_per_cu = 8;
+};
+
+struct Timer {
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;   // pairs of events
+    std::vector<int> kind;          // kind of each recorded pair
+    size_t used = 0;
+    double ms[GBR_K_COUNT] = {0};
+    int64_t count[GBR_K_COUNT] = {0};
+};
+
+}  // namespace gbr
+
+struct gbr_ctx {
+    int device = 0;
+    int n_cu = 256;
+    gbr_gb_params prm{};
+    int32_t n_rep = 0, n_atoms = 0, max_n = 0;
+    int64_t n_pairs = 0;
+    std::vector<int32_t> h_atom_off;
+    int32_t* atom_off = nullptr;     // [n_rep+1]
+    int2* tiles = nullptr;           // per-atom tiles {rep, tile}
+    int32_t n_tiles = 0;
+    gbr::PairList lists[4];          // NI = 1, 2, 4, 8
+    int ni_born = 4, ni_energy = 4, ni_chain = 4;
+    gbr::LaunchShape shape;
+    // workspace
+    int64_t* psi_fx = nullptr;       // [N] sum_j h_ij (2^40)
+    int64_t* dEdR_fx = nullptr;      // [N] pair part of dE/dR_i (2^40)
+    double* dEdR = nullptr;          // [N] total dE/dR_i
+    float* chain_c = nullptr;        // [N] (dE/dR)(dR/dpsi)(rho~/2)
+    int64_t* ke_fx = nullptr;        // [n_rep] (2^32)
+    int32_t* ex_nH = nullptr;        // [n_rep]
+    int32_t* ex_ne = nullptr;
+    double* ex_eps = nullptr;
+    float* ex_vscale = nullptr;
+    uint64_t* step = nullptr;        // [2] current step, next step
+    uint32_t* err = nullptr;         // device error word
+    gbr::Timer timer;
+    // captured per-step graphs (plain, MC, EX, MC+EX)
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t graph_key[4] = {0, 0, 0, 0};
+    hipStream_t cap_stream = nullptr;
+};
+
+namespace gbr {
+
+struct GBConstH {
+    float ke, ke_in, tau, offset;
+    double ke_d, ke_in_d, tau_d, offset_d, alpha, beta, gamma;
+};
+GBConstH make_const(const gbr_gb_params& p);
+
+// kernel launchers (pair kernels) ----------------------------------------
+hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho,
+                            const float* screen, hipStream_t s);
+hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q,
+                              const float* R, const float* sigma, const float* eps,
+                              int64_t* force_fx, int64_t* energy_fx, int64_t* dEdq_fx,
+                              hipStream_t s);
+hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rho,
+                             const float* screen, int64_t* force_fx, int64_t* dEdrho_fx,
+                             hipStream_t s);
+
+// per-atom kernels ------------------------------------------------------------
+hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
+hipError_t launch_born_finalize(const gbr_ctx* c, const float* rho, float* R, float* dRdpsi,
+                                double* psi, hipStream_t s);
+hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const float* R,
+                       const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, hipStream_t s);
+hipError_t launch_rho_finalize(const gbr_ctx* c, const float* rho, const float* R,
+                               const float* dRdpsi, const double* psi, int64_t* dEdrho_fx,
+                               hipStream_t s);
+hipError_t launch_energies(const gbr_ctx* c, const int64_t* e, double* out, hipStream_t s);
+hipError_t launch_fx_to_float(const gbr_ctx* c, const int64_t* src, int comps, int bits,
+                              const double* scale, int sign, float* dst, hipStream_t s);
+
+// dynamics ---------------------------------------------------------------------
+struct MDArgs {
+    gbr_md_state st;
+    gbr_md_params pr;
+    uint64_t seed;
+};
+hipError_t launch_step_begin(const gbr_ctx* c, hipStream_t s);
+hipError_t launch_set_step(const gbr_ctx* c, uint64_t step0, hipStream_t s);
+hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, hipStream_t s);
+hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s);
+hipError_t launch_mc(const gbr_ctx* c, const MDArgs& a, hipStream_t s);
+hipError_t launch_titration(const gbr_ctx* c, const float* xyz, const float* q, const float* R,
+                            const gbr_sites& sites, const int32_t* cand, int32_t n_cand,
+                            double* dE, hipStream_t s);
+hipError_t launch_exchange_inputs(const gbr_ctx* c, const gbr_md_state& st,
+                                  const gbr_md_params& pr, int32_t* nH, int32_t* ne,
+                                  double* epsT, hipStream_t s);
+hipError_t launch_exchange(const gbr_ctx* c, const gbr_grid& g, uint64_t attempt,
+                           const uint64_t* attempt_from_step, int32_t ex_every,
+                           const int32_t* nH, const int32_t* ne, const double* epsT,
+                           int32_t* target_idx, int32_t* grid_rep, float* vscale,
+                           uint32_t* ex_stats, uint64_t seed, hipStream_t s);
+hipError_t launch_apply_vscale(const gbr_ctx* c, const float* vscale, float* v, hipStream_t s);
+
+}  // namespace gbr

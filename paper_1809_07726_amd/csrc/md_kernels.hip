@@ -1,0 +1,508 @@
+// md_kernels.hip -- the cheap O(N) and O(R) parts of a C(pH,E)MD / REMD
+// step that stay on the device: the BAOAB Langevin updates, the tether, the
+// titration Monte Carlo attempts, and the replica-exchange attempts.
+#include "gbr_device.h"
+#include "gbr_internal.h"
+
+using namespace gbr;
+
+namespace {
+
+// ----------------------------------------------------------- step counter
+// step[0] = index of the step being executed, step[1] = index of the next one.
+__global__ void k_set_step(uint64_t* step, uint64_t step0) { step[1] = step0; }
+__global__ void k_step_begin(uint64_t* step) {
+    step[0] = step[1];
+    step[1] = step[1] + 1;
+}
+
+// ------------------------------------------------------ B, A, O, A stages
+// v += dt/2 F/m;  x += dt/2 v;  v = c1 v + c2 sqrt(kT/m) xi;  x += dt/2 v.
+// Also clears the accumulators of the force evaluation that follows.
+__global__ __launch_bounds__(256) void k_md_first(
+    const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
+    const uint64_t* __restrict__ step, uint64_t seed, double hdt, double c1, double c2,
+    const float* __restrict__ mass, const double* __restrict__ T_vals,
+    const int32_t* __restrict__ target_idx, float* __restrict__ xyz, float* __restrict__ v,
+    int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ psi_fx,
+    int64_t* __restrict__ dEdR_fx, int64_t* __restrict__ ke_fx)
+{
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int2 tl = tiles[t];
+    const int rep = tl.x;
+    const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
+    const int li = tl.y * 64 + lane;
+    if (tl.y == 0 && lane < 4) energy_fx[4 * rep + lane] = 0;
+    if (tl.y == 0 && lane == 0) ke_fx[rep] = 0;
+    if (li >= n) return;
+    const int a = a0 + li;
+    const uint64_t nstep = step[0];
+    const double kT = KB * T_vals[target_idx[3 * rep + 2]];
+    const double im = ACC_CONV / (double)mass[a];
+    const double sd = sqrt(kT * im);
+    double xi[4];
+    normal2(draw(seed, 2u * li, (uint32_t)rep, nstep, STREAM_O), xi[0], xi[1]);
+    normal2(draw(seed, 2u * li + 1u, (uint32_t)rep, nstep, STREAM_O), xi[2], xi[3]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t idx = (int64_t)d * ntot + a;
+        double vv = v[idx], xx = xyz[idx];
+        vv += hdt * from_fixed(force_fx[idx], INV_FX_FORCE) * im;
+        xx += hdt * vv;
+        vv = c1 * vv + c2 * sd * xi[d];
+        xx += hdt * vv;
+        v[idx] = (float)vv;
+        xyz[idx] = (float)xx;
+        force_fx[idx] = 0;
+    }
+    psi_fx[a] = 0;
+    dEdR_fx[a] = 0;
+}
+
+// Tether k |x - x0|^2 added to the forces and the replica's energy slot 3;
+// then (kick) v += dt/2 F/m and the kinetic energy.
+__global__ __launch_bounds__(256) void k_md_last(
+    const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
+    double hdt, double k_t, const float* __restrict__ mass, const float* __restrict__ x0,
+    const float* __restrict__ xyz, float* __restrict__ v, int64_t* __restrict__ force_fx,
+    int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx, int kick,
+    uint32_t* __restrict__ err)
+{
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int2 tl = tiles[t];
+    const int rep = tl.x;
+    const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
+    const int li = tl.y * 64 + lane;
+    double et = 0.0, ke = 0.0;
+    if (li < n) {
+        const int a = a0 + li;
+        const double m = mass[a], im = ACC_CONV / m;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int64_t idx = (int64_t)d * ntot + a;
+            const double dx = (double)xyz[idx] - (double)x0[idx];
+            et += k_t * dx * dx;
+            const int64_t f = force_fx[idx] + to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
+            force_fx[idx] = f;
+            double vv = v[idx];
+            if (kick) {
+                vv += hdt * from_fixed(f, INV_FX_FORCE) * im;
+                v[idx] = (float)vv;
+            }
+            ke += 0.5 * m * (double)(float)vv * (double)(float)vv / ACC_CONV;
+        }
+    }
+    const double se = wave_sum_d(et), sk = wave_sum_d(ke);
+    if (lane == 0) {
+        atomic_add_fx(&energy_fx[4 * rep + 3], to_fixed(se, FX_ENERGY, err));
+        atomic_add_fx(&ke_fx[rep], to_fixed(sk, FX_ENERGY, err));
+    }
+}
+
+__global__ void k_ke_out(int n_rep, const int64_t* __restrict__ ke_fx, double* __restrict__ ke) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n_rep) ke[r] = from_fixed(ke_fx[r], INV_FX_ENERGY);
+}
+
+// ------------------------------------------------------------ titration
+// Electrostatic energy change of giving site `site` the charges of state
+// `nw`, at fixed Born radii, computed by one workgroup:
+//   dE = sum_k d_k (K q)_k + 1/2 sum_{k,l} d_k d_l K_kl,   d = q_new - q on the site.
+constexpr int MAX_SITE = 64;
+constexpr int TB = 256;
+
+struct SiteSmem {
+    float x[MAX_SITE], y[MAX_SITE], z[MAX_SITE], R[MAX_SITE], d[MAX_SITE], qn[MAX_SITE];
+    int atom[MAX_SITE];
+    double red[TB / 64];
+};
+
+__device__ double block_sum_d(double v, double* red) {
+    v = wave_sum_d(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return s;
+}
+
+__device__ double site_delta_e(SiteSmem& sm, int m, int a0, int n, int ntot,
+                               const float* __restrict__ xyz, const float* __restrict__ q,
+                               const float* __restrict__ R, float ke_in, float ketau)
+{
+    float lin = 0.0f;
+    for (int j = a0 + (int)threadIdx.x; j < a0 + n; j += blockDim.x) {
+        const float xj = xyz[j], yj = xyz[ntot + j], zj = xyz[2 * ntot + j];
+        const float qj = q[j], Rj = R[j];
+        float acc = 0.0f;
+        for (int k = 0; k < m; ++k) {
+            float K;
+            if (sm.atom[k] == j) {
+                K = -ketau / Rj;
+            } else {
+                const float dx = xj - sm.x[k], dy = yj - sm.y[k], dz = zj - sm.z[k];
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rinv = frsq(r2);
+                const float ex = fexp_neg(0.25f * r2 / (sm.R[k] * Rj));
+                const float finv = frsq(__builtin_fmaf(sm.R[k] * Rj, ex, r2));
+                K = ke_in * rinv - ketau * finv;
+            }
+            acc += sm.d[k] * K;
+        }
+        lin += acc * qj;
+    }
+    float quad = 0.0f;
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+        const int k = t / m, l = t % m;
+        float K;
+        if (k == l) {
+            K = -ketau / sm.R[k];
+        } else {
+            const float dx = sm.x[l] - sm.x[k], dy = sm.y[l] - sm.y[k], dz = sm.z[l] - sm.z[k];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float rinv = frsq(r2);
+            const float ex = fexp_neg(0.25f * r2 / (sm.R[k] * sm.R[l]));
+            const float finv = frsq(__builtin_fmaf(sm.R[k] * sm.R[l], ex, r2));
+            K = ke_in * rinv - ketau * finv;
+        }
+        quad += sm.d[k] * sm.d[l] * K;
+    }
+    return block_sum_d((double)lin + 0.5 * (double)quad, sm.red);
+}
+
+__device__ void load_site(SiteSmem& sm, int m, int slot0, int nw, int ms, int ntot,
+                          const int32_t* __restrict__ site_atoms, const float* __restrict__ state_q,
+                          const float* __restrict__ xyz, const float* __restrict__ q,
+                          const float* __restrict__ R)
+{
+    for (int k = threadIdx.x; k < m; k += blockDim.x) {
+        const int a = site_atoms[slot0 + k];
+        sm.atom[k] = a;
+        sm.x[k] = xyz[a]; sm.y[k] = xyz[ntot + a]; sm.z[k] = xyz[2 * ntot + a];
+        sm.R[k] = R[a];
+        sm.qn[k] = state_q[(int64_t)(slot0 + k) * ms + nw];
+        sm.d[k] = sm.qn[k] - q[a];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(TB) void k_titration(
+    const int32_t* __restrict__ atom_off, int n_rep, int ntot, const float* __restrict__ xyz,
+    const float* __restrict__ q, const float* __restrict__ R, gbr_sites S,
+    const int32_t* __restrict__ cand, int n_cand, float ke_in, float ketau,
+    double* __restrict__ dE, uint32_t* __restrict__ err)
+{
+    __shared__ SiteSmem sm;
+    const int c = blockIdx.x;
+    if (c >= n_cand) return;
+    const int site = cand[2 * c], nw = cand[2 * c + 1];
+    bool bad = site < 0 || site >= S.n_sites;
+    int m = 0, rep = 0;
+    if (!bad) {
+        m = S.site_off[site + 1] - S.site_off[site];
+        rep = S.site_rep[site];
+        bad = nw < 0 || nw >= S.n_states[site] || m > MAX_SITE || m < 1 || rep < 0 || rep >= n_rep;
+    }
+    if (bad) {
+        if (threadIdx.x == 0) {
+            raise_error(err, GBR_ERR_SITE);
+            dE[c] = __builtin_nan("");
+        }
+        return;
+    }
+    load_site(sm, m, S.site_off[site], nw, S.max_states, ntot, S.site_atoms, S.state_q, xyz, q, R);
+    const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
+    const double v = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau);
+    if (threadIdx.x == 0) dE[c] = v;
+}
+
+// One protonation attempt, then one redox attempt, for replica blockIdx.x.
+//   dG = dE - [G_ref(s') - G_ref(s)] + kT ln10 (pH - pKa_ref)(N_H(s') - N_H(s))   (pH)
+//   dG = dE - [G_ref(s') - G_ref(s)] + F (E - E0_ref)(N_e(s') - N_e(s))            (redox)
+// accepted iff dG <= 0 or u < exp(-dG/kT); accepted charges are written before
+// the next attempt reads q.
+__global__ __launch_bounds__(TB) void k_mc(
+    const int32_t* __restrict__ atom_off, int n_rep, int ntot, const uint64_t* __restrict__ step,
+    uint64_t seed, const float* __restrict__ xyz, float* __restrict__ q,
+    const float* __restrict__ R, gbr_sites S, gbr_grid G, int32_t* __restrict__ site_state,
+    const int32_t* __restrict__ target_idx, uint32_t* __restrict__ mc_stats, float ke_in,
+    float ketau, uint32_t* __restrict__ err)
+{
+    __shared__ SiteSmem sm;
+    __shared__ int s_site, s_new, s_acc;
+    const int rep = blockIdx.x;
+    if (rep >= n_rep) return;
+    const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
+    const uint64_t nstep = step[0];
+    const int ms = S.max_states;
+    for (int type = 0; type < 2; ++type) {
+        U4 w{0, 0, 0, 0};
+        if (threadIdx.x == 0) {
+            const int s0 = S.rep_site_off[rep], s1 = S.rep_site_off[rep + 1];
+            int cnt = 0;
+            for (int k = s0; k < s1; ++k) cnt += S.site_type[k] == type;
+            s_site = -1;
+            if (cnt > 0) {
+                w = draw(seed, 0u, (uint32_t)rep, nstep, type == 0 ? STREAM_MCPH : STREAM_MCRED);
+                const uint32_t pick = choose(w.x, (uint32_t)cnt);
+                int site = -1;
+                for (int k = s0, mm = 0; k < s1; ++k) {
+                    if (S.site_type[k] != type) continue;
+                    if ((uint32_t)mm == pick) { site = k; break; }
+                    ++mm;
+                }
+                const int cur = site_state[site];
+                const uint32_t off = choose(w.y, (uint32_t)(S.n_states[site] - 1));
+                s_new = (int)off < cur ? (int)off : (int)off + 1;
+                s_site = site;
+                if (S.site_off[site + 1] - S.site_off[site] > MAX_SITE) {
+                    raise_error(err, GBR_ERR_SITE);
+                    s_site = -1;
+                }
+            }
+        }
+        __syncthreads();
+        const int site = s_site;
+        if (site < 0) { __syncthreads(); continue; }
+        const int nw = s_new;
+        const int m = S.site_off[site + 1] - S.site_off[site];
+        load_site(sm, m, S.site_off[site], nw, ms, ntot, S.site_atoms, S.state_q, xyz, q, R);
+        const double dEel = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau);
+        if (threadIdx.x == 0) {
+            const int cur = site_state[site];
+            const double T = G.T_vals[target_idx[3 * rep + 2]];
+            const double kT = KB * T;
+            double dG = dEel - (S.G_ref[site * ms + nw] - S.G_ref[site * ms + cur]);
+            if (type == 0) {
+                const double pH = G.pH_vals[target_idx[3 * rep + 1]];
+                dG += kT * LN10 * (pH - S.ref_value[site])
+                      * (double)(S.state_nH[site * ms + nw] - S.state_nH[site * ms + cur]);
+            } else {
+                const double Ev = G.E_vals[target_idx[3 * rep + 0]];
+                dG += FARADAY * (Ev - S.ref_value[site])
+                      * (double)(S.state_ne[site * ms + nw] - S.state_ne[site * ms + cur]);
+            }
+            const double u = uniform53(w.z, w.w);
+            const bool acc = dG <= 0.0 || u < exp(-dG / kT);
+            if (!(dG == dG)) raise_error(err, GBR_ERR_NONFINITE);
+            s_acc = acc ? 1 : 0;
+            if (acc) site_state[site] = nw;
+            if (mc_stats) {
+                mc_stats[2 * site] += 1;
+                if (acc) mc_stats[2 * site + 1] += 1;
+            }
+        }
+        __syncthreads();
+        if (s_acc)
+            for (int k = threadIdx.x; k < m; k += blockDim.x) q[sm.atom[k]] = sm.qn[k];
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- replica exchange
+// Per replica: protons, electrons and the energy entering the temperature
+// exchange: U - sum G_ref(s) + sum_redox F (E - E0_ref) N_e(s)  (mode 0) or U (mode 1).
+__global__ void k_exchange_inputs(int n_rep, gbr_sites S, gbr_grid G,
+                                  const int32_t* __restrict__ site_state,
+                                  const int32_t* __restrict__ target_idx,
+                                  const int64_t* __restrict__ energy_fx, int eps_mode,
+                                  int32_t* __restrict__ nH, int32_t* __restrict__ ne,
+                                  double* __restrict__ epsT)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rep) return;
+    const int ms = S.max_states;
+    int h = 0, e = 0;
+    double extra = 0.0;
+    const double Ev = G.E_vals[target_idx[3 * r]];
+    if (S.rep_site_off) {
+        for (int k = S.rep_site_off[r]; k < S.rep_site_off[r + 1]; ++k) {
+            const int st = site_state[k];
+            h += S.state_nH[k * ms + st];
+            e += S.state_ne[k * ms + st];
+            extra -= S.G_ref[k * ms + st];
+            if (S.site_type[k] == GBR_SITE_REDOX)
+                extra += FARADAY * (Ev - S.ref_value[k]) * (double)S.state_ne[k * ms + st];
+        }
+    }
+    double U = 0.0;
+    for (int c = 0; c < 4; ++c) U += from_fixed(energy_fx[4 * r + c], INV_FX_ENERGY);
+    nH[r] = h;
+    ne[r] = e;
+    epsT[r] = eps_mode == 0 ? U + extra : U;
+}
+
+// One thread per grid point.  The attempt index is `attempt` or, when
+// step_dev is given, (step + 1) / ex_every - 1 for the step being executed.
+__global__ void k_exchange(gbr_grid G, uint64_t attempt, const uint64_t* __restrict__ step_dev,
+                           int ex_every, const int32_t* __restrict__ nH,
+                           const int32_t* __restrict__ ne, const double* __restrict__ epsT,
+                           int32_t* __restrict__ target_idx, int32_t* __restrict__ grid_rep,
+                           float* __restrict__ vscale, uint32_t* __restrict__ ex_stats,
+                           uint64_t seed)
+{
+    const int Gp = G.nE * G.npH * G.nT;
+    const int gg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gg >= Gp * G.n_inst) return;
+    const uint64_t a = step_dev ? (step_dev[0] + 1) / (uint64_t)ex_every - 1 : attempt;
+    const int d = G.dim_order[a % (uint64_t)G.n_dims];
+    const int parity = (int)((a / (uint64_t)G.n_dims) & 1);
+    const int inst = gg / Gp, g = gg % Gp;
+    const int c[3] = {g / (G.npH * G.nT), (g / G.nT) % G.npH, g % G.nT};
+    const int sz[3] = {G.nE, G.npH, G.nT};
+    const int k = c[d];
+    const bool lower = (k & 1) == parity && k + 1 < sz[d];
+    const bool upper = k >= 1 && ((k - 1) & 1) == parity;
+    const int ri = grid_rep[gg];
+    if (!lower) {
+        if (!upper) vscale[ri] = 1.0f;
+        return;
+    }
+    int c2[3] = {c[0], c[1], c[2]};
+    c2[d] = k + 1;
+    const int gu = inst * Gp + (c2[0] * G.npH + c2[1]) * G.nT + c2[2];
+    const int rj = grid_rep[gu];
+    double delta;
+    if (d == GBR_DIM_PH) {
+        delta = LN10 * (G.pH_vals[k] - G.pH_vals[k + 1]) * (double)(nH[ri] - nH[rj]);
+    } else if (d == GBR_DIM_E) {
+        const double kT = KB * G.T_vals[c[2]];
+        delta = FARADAY / kT * (G.E_vals[k] - G.E_vals[k + 1]) * (double)(ne[ri] - ne[rj]);
+    } else {
+        const double bi = 1.0 / (KB * G.T_vals[k]), bj = 1.0 / (KB * G.T_vals[k + 1]);
+        delta = (bi - bj) * (epsT[ri] - epsT[rj]);
+    }
+    const U4 w = draw(seed, 0u, (uint32_t)gg, a, STREAM_EX);
+    const double u = uniform53(w.x, w.y);
+    const bool acc = delta >= 0.0 || u < exp(delta);
+    const int GT = Gp * G.n_inst;
+    if (ex_stats) {
+        ex_stats[d * GT + gg] += 1;
+        if (acc) ex_stats[3 * GT + d * GT + gg] += 1;
+    }
+    float si = 1.0f, sj = 1.0f;
+    if (acc) {
+        target_idx[3 * ri + d] = k + 1;
+        target_idx[3 * rj + d] = k;
+        grid_rep[gg] = rj;
+        grid_rep[gu] = ri;
+        if (d == GBR_DIM_T) {
+            si = (float)sqrt(G.T_vals[k + 1] / G.T_vals[k]);
+            sj = (float)sqrt(G.T_vals[k] / G.T_vals[k + 1]);
+        }
+    }
+    vscale[ri] = si;
+    vscale[rj] = sj;
+}
+
+__global__ void k_apply_vscale(int ntot, int n_rep, const int32_t* __restrict__ atom_off,
+                               const float* __restrict__ vscale, float* __restrict__ v)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ntot) return;
+    int lo = 0, hi = n_rep;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (atom_off[mid] <= a) lo = mid; else hi = mid;
+    }
+    const float s = vscale[lo];
+    if (s != 1.0f) {
+        v[a] *= s;
+        v[ntot + a] *= s;
+        v[2 * ntot + a] *= s;
+    }
+}
+
+int tile_grid(const gbr_ctx* c) { return (c->n_tiles + 3) / 4; }
+
+}  // namespace
+
+namespace gbr {
+
+hipError_t launch_set_step(const gbr_ctx* c, uint64_t step0, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, c->step, step0);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_begin(const gbr_ctx* c, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, c->step);
+    return hipGetLastError();
+}
+
+hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, hipStream_t s) {
+    const double hdt = 0.5 * a.pr.dt;
+    const double c1 = exp(-a.pr.gamma * a.pr.dt);
+    const double c2 = sqrt(1.0 - c1 * c1);
+    hipLaunchKernelGGL(k_md_first, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
+                       c->atom_off, c->n_atoms, c->step, a.seed, hdt, c1, c2, a.pr.mass,
+                       a.pr.grid.T_vals, a.st.target_idx, a.st.xyz, a.st.v, a.st.force_fx,
+                       a.st.energy_fx, c->psi_fx, c->dEdR_fx, c->ke_fx);
+    return hipGetLastError();
+}
+
+hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s) {
+    hipLaunchKernelGGL(k_md_last, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
+                       c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.mass, a.pr.x0,
+                       a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx, kick, c->err);
+    if (a.st.ke)
+        hipLaunchKernelGGL(k_ke_out, dim3((c->n_rep + 255) / 256), dim3(256), 0, s, c->n_rep,
+                           c->ke_fx, a.st.ke);
+    return hipGetLastError();
+}
+
+hipError_t launch_mc(const gbr_ctx* c, const MDArgs& a, hipStream_t s) {
+    const GBConstH k = make_const(c->prm);
+    hipLaunchKernelGGL(k_mc, dim3(c->n_rep), dim3(TB), 0, s, c->atom_off, c->n_rep, c->n_atoms,
+                       c->step, a.seed, a.st.xyz, a.st.q, a.st.R, a.pr.sites, a.pr.grid,
+                       a.st.site_state, a.st.target_idx, a.st.mc_stats, k.ke_in,
+                       (float)(k.ke_d * k.tau_d), c->err);
+    return hipGetLastError();
+}
+
+hipError_t launch_titration(const gbr_ctx* c, const float* xyz, const float* q, const float* R,
+                            const gbr_sites& sites, const int32_t* cand, int32_t n_cand,
+                            double* dE, hipStream_t s) {
+    if (n_cand <= 0) return hipSuccess;
+    const GBConstH k = make_const(c->prm);
+    hipLaunchKernelGGL(k_titration, dim3(n_cand), dim3(TB), 0, s, c->atom_off, c->n_rep,
+                       c->n_atoms, xyz, q, R, sites, cand, n_cand, k.ke_in,
+                       (float)(k.ke_d * k.tau_d), dE, c->err);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange_inputs(const gbr_ctx* c, const gbr_md_state& st,
+                                  const gbr_md_params& pr, int32_t* nH, int32_t* ne,
+                                  double* epsT, hipStream_t s) {
+    hipLaunchKernelGGL(k_exchange_inputs, dim3((c->n_rep + 127) / 128), dim3(128), 0, s, c->n_rep,
+                       pr.sites, pr.grid, st.site_state, st.target_idx, st.energy_fx, pr.eps_mode,
+                       nH, ne, epsT);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(const gbr_ctx* c, const gbr_grid& g, uint64_t attempt,
+                           const uint64_t* attempt_from_step, int32_t ex_every,
+                           const int32_t* nH, const int32_t* ne, const double* epsT,
+                           int32_t* target_idx, int32_t* grid_rep, float* vscale,
+                           uint32_t* ex_stats, uint64_t seed, hipStream_t s) {
+    (void)c;
+    const int total = g.n_inst * g.nE * g.npH * g.nT;
+    hipLaunchKernelGGL(k_exchange, dim3((total + 127) / 128), dim3(128), 0, s, g, attempt,
+                       attempt_from_step, ex_every, nH, ne, epsT, target_idx, grid_rep, vscale,
+                       ex_stats, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_vscale(const gbr_ctx* c, const float* vscale, float* v, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply_vscale, dim3((c->n_atoms + 255) / 256), dim3(256), 0, s,
+                       c->n_atoms, c->n_rep, c->atom_off, vscale, v);
+    return hipGetLastError();
+}
+
+}  // namespace gbr

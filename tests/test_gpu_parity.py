@@ -1,0 +1,106 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same
+seeded inputs: Born radii, energies and forces, titration energy changes;
+determinism; every register-blocking variant; ragged and uneven batches."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import E_TOL, F_TOL, R_TOL, gpu_eval, rms_rel
+from paper_1809_07726_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_batch(b, grads=True):
+    off = b["atom_off"]
+    E, gx, gq, gr = oracle.eval_batch(off, b["xyz"], b["q"], b["rho"], b["screen"], b["sigma"], b["eps"])
+    psi, R, _ = oracle.born_batch(off, b["xyz"], b["rho"], b["screen"])
+    return {"E": E, "F": -gx, "dEdq": gq, "dEdrho": gr, "R": R, "psi": psi}
+
+
+def _check(b, g, o, grads=False):
+    off = b["atom_off"]
+    assert np.abs(g["R"] / o["R"] - 1).max() < R_TOL
+    for r in range(off.size - 1):
+        a, c = off[r], off[r + 1]
+        Eg, Eo = g["E"][r], o["E"][r]
+        tot_o = Eo.sum()
+        assert abs(Eg[4] - tot_o) <= E_TOL * abs(tot_o), (r, Eg, Eo)
+        assert abs(Eg[0] - Eo[0]) <= E_TOL * abs(Eo[0]), (r, Eg, Eo)
+        assert abs(Eg[1] - Eo[1]) <= E_TOL * abs(Eo).sum()
+        assert abs(Eg[2] - Eo[2]) <= E_TOL * abs(Eo).sum()
+        if c - a > 1:
+            assert rms_rel(g["F"][a:c], o["F"][a:c]) < F_TOL, r
+            if grads:
+                assert rms_rel(g["dEdq"][a:c], o["dEdq"][a:c]) < F_TOL
+                assert rms_rel(g["dEdrho"][a:c], o["dEdrho"][a:c]) < F_TOL
+
+
+def test_c0_single_replica():
+    b = synth.make_config(0)
+    _check(b, gpu_eval(b, True, True), _oracle_batch(b), grads=True)
+
+
+def test_replicas_with_distinct_geometry():
+    """Replicas of the 1024-atom E,T,pH system with independent jitter, so a
+    replica-indexing mistake cannot hide behind identical copies."""
+    b = synth.make_config(2, n_rep=6, per_replica_jitter=True)
+    _check(b, gpu_eval(b), _oracle_batch(b))
+
+
+def test_ragged_uneven_replicas():
+    """Replica sizes that are not multiples of the 64-atom tile, including a
+    single atom and sizes smaller than one tile."""
+    sizes = [1, 2, 37, 64, 65, 100, 257, 500, 700]
+    systems = [synth.draw_system(n, 500 + n, 1 if n >= 16 else 0, 1 if n >= 16 else 0) for n in sizes]
+    b = synth.assemble(systems, 1, (-0.2,), (7.0,), (300.0,), (0,))
+    _check(b, gpu_eval(b, True, True), _oracle_batch(b), grads=True)
+
+
+@pytest.mark.parametrize("ni", [1, 2, 4, 8])
+def test_every_register_blocking(ni):
+    b = synth.make_config(1, n_atoms=700, n_rep=2, per_replica_jitter=True)
+    _check(b, gpu_eval(b, True, True, blocking=(ni, ni, ni)), _oracle_batch(b), grads=True)
+
+
+def test_bitwise_reproducible_and_newton_balanced():
+    b = synth.make_config(2, n_rep=4, per_replica_jitter=True)
+    g1 = gpu_eval(b, True, True)
+    g2 = gpu_eval(b, True, True)
+    assert np.array_equal(g1["F_fx"], g2["F_fx"])
+    assert np.array_equal(g1["E_fx"], g2["E_fx"])
+    assert np.array_equal(g1["R"], g2["R"])
+    # Newton's third law: each pair force enters the i-side and the j-side FP32
+    # partial sums, which round differently, so the net force vanishes only to
+    # a few FP32 ulps of the summed magnitudes (the oracle's is zero to FP64).
+    off = b["atom_off"]
+    for r in range(off.size - 1):
+        F = g1["F"][off[r]:off[r + 1]]
+        assert np.abs(F.sum(0)).max() <= 2e-8 * np.abs(F).sum()
+
+
+def test_titration_delta_e_matches_oracle():
+    from paper_1809_07726_amd.gb import Context
+    from gpu_common import to_dev
+    import torch
+    b = synth.make_config(1, n_rep=4, per_replica_jitter=True)
+    d = to_dev(b)
+    ctx = Context(b["atom_off"])
+    t = d.t
+    R, _, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"])
+    cand = np.array([(s, 1) for s in range(b["n_sites"])], np.int32).reshape(-1)
+    dE = ctx.titration_delta_e(t["xyz"], t["q"], R, d, torch.as_tensor(cand)).cpu().numpy()
+    ctx.check()
+    off = b["atom_off"]
+    ms = b["max_states"]
+    for s in range(b["n_sites"]):
+        r = int(np.searchsorted(off, b["site_atoms"][b["site_off"][s]], side="right") - 1)
+        a0, a1 = off[r], off[r + 1]
+        x = b["xyz"][a0:a1]
+        _, Ro, _ = oracle.born(x, b["rho"][a0:a1], b["screen"][a0:a1])
+        sl = slice(b["site_off"][s], b["site_off"][s + 1])
+        idx = b["site_atoms"][sl] - a0
+        qn = b["state_q"].reshape(-1, ms)[sl, 1]
+        ref = oracle.delta_e(x, b["q"][a0:a1], Ro, idx, qn)
+        scale = abs(oracle.elec_energy(x, b["q"][a0:a1], Ro)) / len(idx)
+        assert abs(dE[s] - ref) <= 1e-6 * max(abs(ref), scale), (s, dE[s], ref)
