@@ -1,0 +1,249 @@
+"""Benchmark: batched GB energy+force pair-interactions/s on one MI355X.
+
+Workload (default): the 3-D E,T,pH replica-exchange batch -- 192 replicas
+(8 E x 4 T x 6 pH) of one 1,024-atom synthetic system -- advanced by md_step:
+every step evaluates the Born radii, GB + Coulomb + LJ energy and forces with
+the chain rule, the Langevin update, titration attempts every 10 steps and an
+exchange attempt every 100 steps, all on the device.  A step processes
+192 * 1024 * 1023 / 2 = 100,564,992 pair interactions.
+
+Prints one JSON line (see the keys below).  Timing: W untimed warm-up steps,
+then K steps between two synchronizations.  The pair kernels are timed
+individually with HIP events recorded by the library on the launch stream
+inside the timed region; the dominant one gives the roofline entry.
+
+--gpus N with N > 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FLOPs per unordered pair (FMA = 2; add, sub, mul, div, sqrt,
+# rsqrt, exp, log = 1; compare, select, min/max, abs = 0; per-atom
+# precomputations not counted), from the closed forms of each pass:
+FLOP_BORN = 49     # distance + both HCT descreening terms and their accumulation
+FLOP_ENERGY = 64   # Coulomb + GB + LJ energies, direct forces, dE/dR_i and dE/dR_j
+FLOP_CHAIN = 55    # distance + both dh/dr terms, chain coefficients, forces
+FLOP_PAIR = FLOP_BORN + FLOP_ENERGY + FLOP_CHAIN
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
+PAPER_CONTEXT = {
+    "source": "Table 1: pmemd.cuda.MPI E,pH,T-REMD, 237-atom NAcMP8 system, GB igb=2, "
+              "one NVIDIA Tesla K20X per replica, 216 replicas",
+    "ns_per_day_per_replica": 181, "dt_fs": 2,
+    "step_ms_per_replica": 1e6 / (181e6 / 2.0 / 86400.0) / 1000.0,
+    "pairs_per_s_per_gpu_upper_bound": 237 * 236 / 2 * 181e6 / 2.0 / 86400.0,
+}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--config", type=int, default=2)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--graph", action="store_true", help="time the captured-graph path instead")
+    p.add_argument("--cpu-sample-replicas", type=int, default=0)
+    p.add_argument("--profile-only", action="store_true",
+                   help="short run for rocprofv3: warm-up and a few timed steps, no baselines")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    return p.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1809_07726_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel, launches_bytes_alg):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "pair_kernels_c2_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(b, n_rep_sample, budget_s=15.0):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload:
+    full E+F gradient evaluations of successive replicas until n_rep_sample
+    replicas (0: no limit) or about budget_s seconds of CPU work."""
+    import oracle
+    off = b["atom_off"]
+    t0 = time.perf_counter()
+    pairs = 0
+    done = 0
+    for r in range(b["n_rep"]):
+        if (n_rep_sample and done >= n_rep_sample) or time.perf_counter() - t0 > budget_s:
+            break
+        done += 1
+        a, c = off[r], off[r + 1]
+        oracle.gradient(b["xyz"][a:c], b["q"][a:c], b["rho"][a:c], b["screen"][a:c],
+                        b["sigma"][a:c], b["eps"][a:c])
+        n = c - a
+        pairs += n * (n - 1) // 2
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} of {b['n_rep']} replicas x {off[1] - off[0]} atoms: one FP64 "
+                      f"Born-radii + energy + analytic-gradient evaluation each ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import torch
+    from paper_1809_07726_amd import synth
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch, reference_energies
+
+    torch.cuda.set_device(0)
+    b = synth.make_config(args.config)
+    w = synth.CONFIGS[args.config]
+    b["G_ref"] = reference_energies(b)
+    ctx = Context(b["atom_off"])
+    dev = DeviceBatch.from_numpy(b)
+    md = MD(ctx, dev, b, seed=w.dyn_seed)
+    n_pairs = ctx.n_pairs
+    stream = torch.cuda.current_stream()
+
+    md.run(0, init_forces=True)
+    md.run(args.warmup if not args.profile_only else 3, graph=args.graph)
+    torch.cuda.synchronize()
+    ctx.check()
+    K = args.steps if not args.profile_only else 5
+    ctx.set_timing(not args.graph)
+    ctx.get_timing()                       # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    md.run(K, graph=args.graph)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timing = ctx.get_timing() if not args.graph else {}
+    ctx.set_timing(False)
+    ctx.check()
+    if args.profile_only:
+        if args.copy_calibration:
+            x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+            y = torch.empty_like(x)
+            for _ in range(3):
+                y.copy_(x)
+            torch.cuda.synchronize()
+        print(json.dumps({"profile_only": True, "steps": K, "ms_per_step": 1000 * dt / K}))
+        return
+
+    value = K * n_pairs / dt
+    ms_step = 1000.0 * dt / K
+    # dominant pair kernel
+    flops = {"born_pair": FLOP_BORN, "energy_pair": FLOP_ENERGY, "chain_pair": FLOP_CHAIN}
+    per_kernel = {}
+    for k in flops:
+        ms, cnt = timing.get(k, (0.0, 0))
+        if cnt:
+            avg = ms / cnt
+            per_kernel[k] = {"avg_ms": avg, "launches": cnt,
+                             "tflops": flops[k] * n_pairs / (avg * 1e-3) / 1e12}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"]) if per_kernel else None
+    roofline = None
+    if dom:
+        ach = per_kernel[dom]["tflops"]
+        roofline = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                    "traffic": traffic_from_profile(dom, None),
+                    "avg_launch_ms": per_kernel[dom]["avg_ms"],
+                    "flop_per_pair": flops[dom], "pairs_per_launch": n_pairs}
+    pair_ms = sum(v["avg_ms"] for v in per_kernel.values())
+    all_pairs_tflops = FLOP_PAIR * n_pairs / (pair_ms * 1e-3) / 1e12 if pair_ms else None
+
+    # batched vs per-replica plain E+F evaluation (same kernels, one launch sequence per replica)
+    evals = {}
+    t = dev.t
+    R, dR, psi = ctx.born_radii(t["xyz"], t["rho"], t["screen"])
+    for _ in range(3):
+        R, dR, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"], want_psi=False)
+        ctx.energy_forces(t["xyz"], t["q"], t["rho"], t["screen"], t["sigma"], t["eps"], R, dR)
+    torch.cuda.synchronize()
+    n_eval = 20
+    t0 = time.perf_counter()
+    for _ in range(n_eval):
+        R, dR, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"], want_psi=False)
+        ctx.energy_forces(t["xyz"], t["q"], t["rho"], t["screen"], t["sigma"], t["eps"], R, dR)
+    torch.cuda.synchronize()
+    evals["batched_eval_ms"] = 1000 * (time.perf_counter() - t0) / n_eval
+    if not args.no_plain:
+        off = b["atom_off"]
+        n0 = int(off[1] - off[0])
+        pctx = Context(np.array([0, n0], np.int32))
+        N = ctx.n_atoms
+        reps = []
+        for r in range(b["n_rep"]):
+            a, c = off[r], off[r + 1]
+            sl = lambda key: t[key][a:c].contiguous()
+            xyz = torch.stack([t["xyz"][a:c], t["xyz"][N + a:N + c], t["xyz"][2 * N + a:2 * N + c]]).reshape(-1).contiguous()
+            reps.append((xyz, sl("q"), sl("rho"), sl("screen"), sl("sigma"), sl("eps")))
+        def plain_pass():
+            for xyz, q, rho, scr, sig, eps in reps:
+                R1, dR1, _ = pctx.born_radii(xyz, rho, scr, want_psi=False)
+                pctx.energy_forces(xyz, q, rho, scr, sig, eps, R1, dR1)
+        plain_pass()
+        torch.cuda.synchronize()
+        n_plain = 3
+        t0 = time.perf_counter()
+        for _ in range(n_plain):
+            plain_pass()
+        torch.cuda.synchronize()
+        evals["plain_eval_ms"] = 1000 * (time.perf_counter() - t0) / n_plain
+        evals["speedup_batched_vs_plain"] = evals["plain_eval_ms"] / evals["batched_eval_ms"]
+        pctx.close()
+    evals["batched_eval_pairs_per_s"] = n_pairs / (evals["batched_eval_ms"] * 1e-3)
+    if "plain_eval_ms" in evals:
+        evals["plain_eval_pairs_per_s"] = n_pairs / (evals["plain_eval_ms"] * 1e-3)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(b, args.cpu_sample_replicas)
+
+    out = {
+        "metric": "GB energy+force pair-interactions/s, batched replicas vs per-replica plain",
+        "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+i64fx",
+        "data": "synthetic",
+        "config": {"workload": w.name, "replicas": int(b["n_rep"]), "atoms_per_replica": int(b["atom_off"][1]),
+                   "grid": "8 E x 4 T x 6 pH", "pairs_per_step": n_pairs, "mc_every": w.mc_every,
+                   "ex_every": w.ex_every, "graph": bool(args.graph)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "pair_kernels": per_kernel,
+        "all_pair_passes_tflops": all_pairs_tflops,
+        "eval": evals,
+        "paper_context": PAPER_CONTEXT,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+"""md_step, titration Monte Carlo and replica exchange on the GPU against the
+oracle: short trajectories (positions, velocities, charges, states,
+energies), exchange decisions on identical inputs, graph replay equal to
+eager launches, and titration statistics (eq. 1, eq. 2)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from common import with_oracle_gref
+from gpu_common import FX_E, soa_to_aos
+from paper_1809_07726_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_md(b, seed, steps_chunks, graph=False, init=True):
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch
+    ctx = Context(b["atom_off"])
+    d = DeviceBatch.from_numpy(b)
+    md = MD(ctx, d, b, seed=seed)
+    snaps = []
+    first = True
+    for n in steps_chunks:
+        md.run(n, init_forces=init and first, graph=graph)
+        first = False
+        torch.cuda.synchronize()
+        N = ctx.n_atoms
+        snaps.append({
+            "xyz": soa_to_aos(d.t["xyz"].cpu().numpy(), N), "v": soa_to_aos(d.t["v"].cpu().numpy(), N),
+            "q": d.t["q"].cpu().numpy().astype(np.float64),
+            "site_state": d.t["site_state"].cpu().numpy().copy() if b["n_sites"] else None,
+            "target_idx": d.t["target_idx"].cpu().numpy().reshape(-1, 3).copy(),
+            "grid_rep": d.t["grid_rep"].cpu().numpy().copy(),
+            "E": md.energy_fx.cpu().numpy().reshape(-1, 4) * FX_E,
+            "F_fx": md.force_fx.cpu().numpy().copy(),
+            "ke": md.ke.cpu().numpy().copy(),
+            "mc_stats": md.mc_stats.cpu().numpy().copy() if md.mc_stats is not None else None,
+        })
+    ctx.check()
+    ctx.close()
+    return snaps
+
+
+def _oracle_md(b, seed, steps_chunks):
+    cfg, st, arr, keep = oracle.make_md(b, seed=seed)
+    oracle.md_run(cfg, st, 0, 0, True)
+    snaps, step = [], 0
+    for n in steps_chunks:
+        oracle.md_run(cfg, st, step, n, False)
+        step += n
+        snaps.append({k: arr[k].copy() for k in ("xyz", "v", "q", "site_state", "target_idx",
+                                                 "grid_rep", "E", "mc_att", "mc_acc")})
+    return snaps
+
+
+def test_md_step_matches_oracle_trajectory():
+    """c0 system: 25 Langevin steps with titration attempts every 10 steps."""
+    b = with_oracle_gref(synth.make_config(0))
+    seed = 2000
+    g = _gpu_md(b, seed, [10, 15])
+    o = _oracle_md(b, seed, [10, 15])
+    for gs, os_ in zip(g, o):
+        x_o = os_["xyz"].reshape(-1, 3)
+        v_o = os_["v"].reshape(-1, 3)
+        assert np.abs(gs["xyz"] - x_o).max() < 2e-4
+        assert np.sqrt(((gs["v"] - v_o) ** 2).sum() / (v_o ** 2).sum()) < 1e-3
+        assert np.array_equal(gs["site_state"], os_["site_state"])
+        assert np.allclose(gs["q"], os_["q"], atol=1e-6)
+        Eo = os_["E"].reshape(-1, 4)
+        assert np.allclose(gs["E"], Eo, rtol=1e-4, atol=1e-3)
+    # the attempts counted on both sides
+    assert g[-1]["mc_stats"][0::2].sum() == o[-1]["mc_att"].sum() == 4
+
+
+def test_md_first_step_is_exact_to_fp32():
+    """One step from rest: the Ornstein-Uhlenbeck noise is the same Philox
+    stream on both sides, so positions agree to FP32 rounding."""
+    b = with_oracle_gref(synth.make_config(0))
+    g = _gpu_md(b, 77, [1])[0]
+    o = _oracle_md(b, 77, [1])[0]
+    assert np.abs(g["xyz"] - o["xyz"].reshape(-1, 3)).max() < 1e-5
+    v_o = o["v"].reshape(-1, 3)
+    assert np.abs(g["v"] - v_o).max() < 1e-4 * np.abs(v_o).max()
+
+
+def test_graph_replay_is_bitwise_equal_to_eager():
+    b = with_oracle_gref(synth.make_config(1, n_atoms=256, n_rep=8))
+    b["ex_every"] = 10
+    eager = _gpu_md(b, 5, [35])[0]
+    graph = _gpu_md(b, 5, [35], graph=True)[0]
+    for k in ("xyz", "v", "q", "site_state", "target_idx", "grid_rep", "F_fx"):
+        assert np.array_equal(eager[k], graph[k]), k
+
+
+def test_replica_grid_md_with_exchanges_matches_oracle():
+    """A 2 x 2 x 2 (E, T, pH) grid, 2 instances, MC every 5 steps and
+    exchanges every 10: targets and states follow the oracle exactly."""
+    base = synth.draw_system(160, 4242, 2, 1)
+    b = synth.assemble([base, synth.jitter_copy(base, 99)], 8, (-0.25, -0.15), (6.0, 7.5),
+                       (300.0, 330.0), (synth.DIM_E, synth.DIM_T, synth.DIM_PH),
+                       mc_every=5, ex_every=10)
+    b = with_oracle_gref(b)
+    chunks = [10, 10, 10, 10]
+    g = _gpu_md(b, 31, chunks)
+    o = _oracle_md(b, 31, chunks)
+    for gs, os_ in zip(g, o):
+        assert np.array_equal(gs["target_idx"], os_["target_idx"].reshape(-1, 3))
+        assert np.array_equal(gs["grid_rep"], os_["grid_rep"])
+        assert np.array_equal(gs["site_state"], os_["site_state"])
+        assert np.abs(gs["xyz"] - os_["xyz"].reshape(-1, 3)).max() < 1e-3
+
+
+def test_exchange_decisions_match_oracle_on_identical_inputs():
+    """192 replicas on the 8 x 6 x 4 grid; random proton / electron counts and
+    energies; 12 consecutive attempts cycle E, T, pH with alternating parity."""
+    from paper_1809_07726_amd.gb import Context, DeviceBatch
+    w = synth.CONFIGS[2]
+    base = synth.draw_system(16, 77, 0, 0)
+    b = synth.assemble([base], 192, w.E_vals, w.pH_vals, w.T_vals, w.dim_order)
+    cfg, st, arr, keep = oracle.make_md(b, seed=123)
+    d = DeviceBatch.from_numpy(b)
+    ctx = Context(b["atom_off"])
+    rng = np.random.default_rng(8)
+    R = b["n_rep"]
+    ti_o, gr_o = b["target_idx"].copy(), b["grid_rep"].copy()
+    ti_g = torch.as_tensor(ti_o.reshape(-1).copy(), device="cuda")
+    gr_g = torch.as_tensor(gr_o.copy(), device="cuda")
+    for a in range(12):
+        nH = rng.integers(0, 6, R).astype(np.int32)
+        ne = rng.integers(0, 2, R).astype(np.int32)
+        ep = rng.normal(-5000.0, 3.0, R)
+        ti_o, gr_o, vs_o, att, acc = oracle.exchange(cfg, a, nH, ne, ep, ti_o, gr_o)
+        vs_g = ctx.remd_exchange(d.grid, a, torch.as_tensor(nH, device="cuda"),
+                                 torch.as_tensor(ne, device="cuda"),
+                                 torch.as_tensor(ep, device="cuda"), ti_g, gr_g, seed=123)
+        torch.cuda.synchronize()
+        assert np.array_equal(ti_g.cpu().numpy().reshape(-1, 3), ti_o), a
+        assert np.array_equal(gr_g.cpu().numpy(), gr_o), a
+        assert np.allclose(vs_g.cpu().numpy(), vs_o, rtol=1e-6)
+        assert acc.sum() > 0
+    ctx.check()
+    ctx.close()
+
+
+@pytest.mark.parametrize("kind,delta", [("ph", -1.0), ("ph", 0.0), ("ph", 0.7),
+                                        ("redox", -0.05), ("redox", 0.03)])
+def test_gpu_titration_statistics(kind, delta):
+    """Frozen isolated site, attempts every step on the GPU: the sampled
+    fraction follows eq. 1 (pH) or eq. 2 (redox potential)."""
+    from paper_1809_07726_amd.gb import reference_energies
+    src = synth.make_config(0, n_atoms=64, seed=31)
+    s = 0 if kind == "ph" else 1
+    a, c = src["site_off"][s], src["site_off"][s + 1]
+    idx = src["site_atoms"][a:c]
+    t = synth.PH_SITE if kind == "ph" else synth.REDOX_SITE
+    sysd = {k: src[k][idx] for k in ("xyz", "x0", "q", "rho", "screen", "sigma", "eps", "mass")}
+    sysd["sites"] = [{"type": t, "atoms": np.arange(c - a), "q_states": src["state_q"].reshape(-1, 2)[a:c],
+                      "nH": [0, 1] if t == 0 else [0, 0], "ne": [0, 0] if t == 0 else [0, 1],
+                      "ref": src["ref_value"][s]}]
+    # 64 independent copies of the site, each its own replica: more samples per step
+    reps = 64
+    E_vals = (synth.E0_REF + delta,) if kind == "redox" else (-0.2,)
+    pH_vals = (synth.PKA_REF + delta,) if kind == "ph" else (7.0,)
+    b = synth.assemble([sysd] * reps, 1, E_vals, pH_vals, (300.0,), (0,), dt=0.0, mc_every=1)
+    b["G_ref"] = reference_energies(b)          # the HIP path's own reference compound
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch
+    ctx = Context(b["atom_off"])
+    d = DeviceBatch.from_numpy(b)
+    md = MD(ctx, d, b, seed=900 + int(100 * delta))
+    md.run(1, init_forces=True)
+    n, occ = 400, 0.0
+    for _ in range(n):
+        md.run(1)
+        occ += d.t["site_state"].float().mean().item()
+    ctx.check()
+    f_hat = occ / n
+    if kind == "ph":
+        f = 1.0 / (1.0 + 10.0 ** delta)
+        up, down = min(1.0, 10.0 ** -delta), min(1.0, 10.0 ** delta)
+    else:
+        x = oracle.constants()["F"] * delta / (oracle.constants()["kB"] * 300.0)
+        f = 1.0 / (1.0 + math.exp(x))
+        up, down = min(1.0, math.exp(-x)), min(1.0, math.exp(x))
+    lam = 1.0 - up - down
+    sigma = math.sqrt(f * (1 - f) / (n * reps) * (1 + lam) / max(1 - lam, 1e-12))
+    assert abs(f_hat - f) <= 4 * sigma + 1.0 / (n * reps), (f_hat, f, sigma)
+    ctx.close()
