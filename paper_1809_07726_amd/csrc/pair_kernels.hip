@@ -5,15 +5,24 @@
 // (r, IB, J) is the set of pairs (i, j) with i in block IB, j in tile J and
 // i < j (local indices), so every unordered pair of every replica belongs to
 // exactly one item; items exist for J >= IB * NI.  One wavefront processes one
-// item: lane l holds the NI atoms i = IB*64*NI + u*64 + l (u < NI) in
-// registers and one atom of the J tile; the J atoms are broadcast one at a time
-// through readlane (scalar registers).  Contributions to i accumulate per lane
-// in FP32; contributions to the broadcast j are summed over the lane's NI
-// atoms and then over the wavefront with DPP, and land in the lane that owns
-// j.  At the end of the item every per-atom partial is rounded to 64-bit fixed
-// point and added with an integer atomic, so the result does not depend on the
-// order in which items run.  Invalid pairs (i >= j, or an I lane past the end
-// of the replica) are removed with selects, never with dummy parameters.
+// item.  Lane l holds the NI atoms i = IB*64*NI + u*64 + l (u < NI) in
+// registers; the J tile is copied to a per-wavefront LDS slice.
+//
+// Rotating j accumulators: in step k (0..63) lane l pairs its i atoms with
+// j = (l + k + 1) mod 64, read from LDS, and adds its contribution into a
+// per-lane accumulator that is first rotated by one lane (DPP wave_rol:1,
+// folded into the add).  The accumulator that lane l adds into in step k
+// therefore always belongs to the j it is working on, and after 64 steps every
+// accumulator is back on the lane of its own j.  This replaces a 64-lane
+// reduction per j with one DPP add per component per step.
+//
+// Contributions to i accumulate per lane in FP32.  At the end of the item
+// every per-atom partial is rounded to 64-bit fixed point and added with an
+// integer atomic, so the result does not depend on the order in which items
+// run.  Invalid pairs (i >= j, j past the end of the replica, I lanes past the
+// end) are removed by zeroing 1/r (or sending r to 1e15 A), which makes every
+// term of the pair exactly zero; I sub-blocks of 64 atoms with no valid pair in
+// an item are skipped with a uniform branch.
 //
 // Items are visited grid-stride by a persistent grid whose block index is
 // remapped so that the blocks of one XCD (blocks are dealt round-robin to the
@@ -25,15 +34,58 @@ using namespace gbr;
 
 namespace {
 
+constexpr int MAXW = 4;                 // wavefronts per workgroup
+constexpr float FAR_R2 = 1.0e30f;       // r^2 used for masked pairs
+constexpr float LOG2E = 1.4426950408889634f;
+
 __device__ __forceinline__ int logical_wave() {
     const int nb = gridDim.x, b = blockIdx.x;
     const int lb = (nb & 7) ? b : ((b & 7) * (nb >> 3) + (b >> 3));
     return lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
 }
 
-__device__ __forceinline__ float sel(bool c, float v) { return c ? v : 0.0f; }
+// acc <- acc[lane + 1 (mod 64)] + c : rotate-and-add, one VALU instruction.
+__device__ __forceinline__ float rot_add(float acc, float c) {
+    return c + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                   0, __builtin_bit_cast(int, acc), 0x134 /* wave_rol:1 */, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct ItemGeom {
+    int rep, a0, n, ibase, jbase, nj, u_lim;
+};
+
+template <int NI>
+__device__ __forceinline__ ItemGeom item_geom(const int2 wi, const int32_t* __restrict__ atom_off) {
+    ItemGeom g;
+    g.rep = wi.x;
+    const int IB = wi.y >> 16, J = wi.y & 0xFFFF;
+    g.a0 = atom_off[g.rep];
+    g.n = atom_off[g.rep + 1] - g.a0;
+    g.ibase = IB * 64 * NI;
+    g.jbase = J * 64;
+    g.nj = min(64, g.n - g.jbase);
+    // I sub-blocks u with a valid pair: ibase + 64u < jbase + nj (and < n)
+    const int span = g.jbase + g.nj - g.ibase;
+    g.u_lim = min(NI, (span + 63) >> 6);
+    return g;
+}
+
+// Far-sphere test for both descreening directions of a pair: with
+// m = max(rt, s) and sx = s / HCT_FAR_XMAX per atom, r >= max(m_i + m_j,
+// sx_i, sx_j) implies r - s_j >= rt_i, r - s_i >= rt_j and s/r <= XMAX for both
+// spheres, so both terms may use the polynomial form.
+__device__ __forceinline__ bool both_far(float r, float mi, float mj, float sxi, float sxj) {
+    return r >= fmaxf(mi + mj, fmaxf(sxi, sxj));
+}
 
 // ------------------------------------------------------------- descreening
+// j tile in LDS: {x, y, z, s}, {rt, m, sx, -}
 template <int NI>
 __global__ __launch_bounds__(256) void k_born_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
@@ -41,192 +93,217 @@ __global__ __launch_bounds__(256) void k_born_pair(
     const float* __restrict__ screen, float offset, int64_t* __restrict__ psi_fx,
     uint32_t* __restrict__ err)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ float4 lds[MAXW][2][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int stride = gridDim.x * (blockDim.x >> 6);
+    const float ixmax = 1.0f / HCT_FAR_XMAX;
     for (int it = logical_wave(); it < n_items; it += stride) {
-        const int2 wi = items[it];
-        const int rep = wi.x, IB = wi.y >> 16, J = wi.y & 0xFFFF;
-        const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
-        float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], acc[NI];
+        const ItemGeom g = item_geom<NI>(items[it], atom_off);
+        float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], mi[NI], sxi[NI], acc[NI];
         int li[NI];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            li[u] = IB * 64 * NI + u * 64 + lane;
-            const int a = a0 + min(li[u], n - 1);
+            li[u] = g.ibase + u * 64 + lane;
+            const int a = g.a0 + min(li[u], g.n - 1);
             xi[u] = xyz[a]; yi[u] = xyz[ntot + a]; zi[u] = xyz[2 * ntot + a];
             rti[u] = rho[a] - offset;
             si[u] = screen[a] * rti[u];
+            mi[u] = fmaxf(rti[u], si[u]);
+            sxi[u] = si[u] * ixmax;
             acc[u] = 0.0f;
         }
-        const int jbase = J * 64;
-        const int lj = jbase + lane;
-        const int ja = a0 + min(lj, n - 1);
-        const float xj = xyz[ja], yj = xyz[ntot + ja], zj = xyz[2 * ntot + ja];
-        const float rtj = rho[ja] - offset, sj = screen[ja] * rtj;
+        {
+            const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
+            const float rt = rho[ja] - offset, s = screen[ja] * rt;
+            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s);
+            lds[wv][1][lane] = make_float4(rt, fmaxf(rt, s), s * ixmax, 0.0f);
+        }
+        wave_lds_fence();
         float accj = 0.0f;
-        const int nj = min(64, n - jbase);
-        for (int k = 0; k < nj; ++k) {
-            const float xk = bcast(xj, k), yk = bcast(yj, k), zk = bcast(zj, k);
-            const float rtk = bcast(rtj, k), sk = bcast(sj, k);
-            const int lk = jbase + k;
+        for (int k = 0; k < 64; ++k) {
+            const int m = (lane + k + 1) & 63;
+            const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
+            const int lj = g.jbase + m;
+            const bool jok = m < g.nj;
             float cj = 0.0f;
 #pragma unroll
             for (int u = 0; u < NI; ++u) {
-                const float dx = xk - xi[u], dy = yk - yi[u], dz = zk - zi[u];
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const bool valid = li[u] < lk;
-                const float rinv = frsq(r2);
-                const float r = r2 * rinv;
-                const float hij = hct_h(r, rinv, rti[u], sk);
-                const float hji = hct_h(r, rinv, rtk, si[u]);
-                acc[u] += sel(valid, hij);
-                cj += sel(valid, hji);
+                if (u < g.u_lim) {
+                    const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    r2 = (jok && li[u] < lj) ? r2 : FAR_R2;
+                    const float rinv = frsq(r2);
+                    const float r = r2 * rinv;
+                    // distant-sphere forms, x = s/r:  h = (x^3/r) G(x^2)
+                    const float xij = p0.w * rinv, yij = xij * xij;
+                    const float xji = si[u] * rinv, yji = xji * xji;
+                    float hij = xij * yij * rinv * poly_G(yij);
+                    float hji = xji * yji * rinv * poly_G(yji);
+                    if (!both_far(r, mi[u], p1.y, sxi[u], p1.z)) {
+                        hij = (r + p0.w <= rti[u]) ? 0.0f : hct_closed(r, rinv, rti[u], p0.w);
+                        hji = (r + si[u] <= p1.x) ? 0.0f : hct_closed(r, rinv, p1.x, si[u]);
+                    }
+                    acc[u] += hij;
+                    cj += hji;
+                }
             }
-            const float tot = wave_sum(cj);
-            accj += (lane == k) ? tot : 0.0f;
+            accj = rot_add(accj, cj);
         }
+        wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u)
-            if (li[u] < n) atomic_add_fx(&psi_fx[a0 + li[u]], to_fixed(acc[u], FX_FORCE, err));
-        if (lj < n) atomic_add_fx(&psi_fx[ja], to_fixed(accj, FX_FORCE, err));
+            if (li[u] < g.n) atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed(acc[u], FX_FORCE, err));
+        if (g.jbase + lane < g.n)
+            atomic_add_fx(&psi_fx[g.a0 + g.jbase + lane], to_fixed(accj, FX_FORCE, err));
     }
 }
 
 // ---------------------------------------------- energy and direct forces
-// Per pair at fixed Born radii:
-//   e_C  = (k_e/eps_in) q_i q_j / r
-//   e_GB = -k_e tau q_i q_j / f,  f^2 = r^2 + R_i R_j exp(-D),  D = r^2 / (4 R_i R_j)
+// Per-atom scaled inputs: qc = q sqrt(k_e/eps_in), L2 = sqrt(log2(e)/4)/R,
+// hs = sigma/2, se = 2 sqrt(eps).  Per pair at fixed Born radii, with
+// tau' = tau eps_in and D = r^2/(4 R_i R_j):
+//   e_C  = qc_i qc_j / r
+//   e_GB = -tau' qc_i qc_j / f,  f^2 = r^2 + R_i R_j exp(-D)
 //   e_LJ = 4 eps_ij (s^12 - s^6),  s = sigma_ij / r
-// (1/r) dE/dr = -(e_C + 6 e4 (2 s^12 - s^6)) / r^2 - e_GB (1 - exp(-D)/4) / f^2
-// dE/dR_i = -e_GB exp(-D) (1 + D) R_j / (2 f^2)
-// dE/dq_i = k_e (1/(eps_in r) - tau/f) q_j
+//   (1/r) dE/dr = -(e_C + 6 e4 (2 s^12 - s^6)) / r^2 + tau' (qc_i qc_j / f^3)(1 - exp(-D)/4)
+//   dE/dR_i = tau' (qc_i qc_j / f^3) exp(-D) (1 + D) R_j / 2
+//   dE/dq_i = sqrt(k_e/eps_in) (1/r - tau'/f) qc_j
+// The factors tau' and sqrt(k_e/eps_in) are applied once per atom at the flush.
+// j tile in LDS: {x, y, z, qc}, {R, L2, hs, se}.
 template <int NI, bool GQ>
 __global__ __launch_bounds__(256) void k_energy_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ q, const float* __restrict__ Rb,
-    const float* __restrict__ sigma, const float* __restrict__ eps, float ke, float ke_in,
-    float tau, int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdR_fx,
+    const float* __restrict__ sigma, const float* __restrict__ eps, float sq_ke_in, float taup,
+    int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdR_fx,
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ float4 lds[MAXW][2][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int stride = gridDim.x * (blockDim.x >> 6);
-    const float ketau = ke * tau;
+    const float lc = 0.60056120439322491f;       // sqrt(log2(e) / 4)
+    const float hl = 0.5f / LOG2E;               // D = D2 / log2(e)
+    const float wq = -0.25f * taup;
     for (int it = logical_wave(); it < n_items; it += stride) {
-        const int2 wi = items[it];
-        const int rep = wi.x, IB = wi.y >> 16, J = wi.y & 0xFFFF;
-        const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
-        float xi[NI], yi[NI], zi[NI], qi[NI], Ri[NI], iRi[NI], hsi[NI], sei[NI];
+        const ItemGeom g = item_geom<NI>(items[it], atom_off);
+        float xi[NI], yi[NI], zi[NI], qi[NI], Ri[NI], Li[NI], hsi[NI], sei[NI];
         float fxi[NI], fyi[NI], fzi[NI], dRi[NI], dqi[NI];
         int li[NI];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            li[u] = IB * 64 * NI + u * 64 + lane;
-            const int a = a0 + min(li[u], n - 1);
+            li[u] = g.ibase + u * 64 + lane;
+            const int a = g.a0 + min(li[u], g.n - 1);
             xi[u] = xyz[a]; yi[u] = xyz[ntot + a]; zi[u] = xyz[2 * ntot + a];
-            qi[u] = q[a]; Ri[u] = Rb[a]; iRi[u] = 1.0f / Ri[u];
-            hsi[u] = 0.5f * sigma[a]; sei[u] = 2.0f * sqrtf(eps[a]);
+            qi[u] = q[a] * sq_ke_in;
+            Ri[u] = Rb[a];
+            Li[u] = lc / Ri[u];
+            hsi[u] = 0.5f * sigma[a];
+            sei[u] = 2.0f * sqrtf(eps[a]);
             fxi[u] = fyi[u] = fzi[u] = dRi[u] = dqi[u] = 0.0f;
         }
-        const int jbase = J * 64;
-        const int lj = jbase + lane;
-        const int ja = a0 + min(lj, n - 1);
-        const float xj = xyz[ja], yj = xyz[ntot + ja], zj = xyz[2 * ntot + ja];
-        const float qj = q[ja], Rj = Rb[ja], iRj = 1.0f / Rj;
-        const float hsj = 0.5f * sigma[ja], sej = 2.0f * sqrtf(eps[ja]);
+        {
+            const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
+            const float Rj = Rb[ja];
+            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], q[ja] * sq_ke_in);
+            lds[wv][1][lane] = make_float4(Rj, lc / Rj, 0.5f * sigma[ja], 2.0f * sqrtf(eps[ja]));
+        }
+        wave_lds_fence();
         float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, dRj = 0.0f, dqj = 0.0f;
-        float e_c = 0.0f, e_gb = 0.0f, e_lj = 0.0f;
-        const int nj = min(64, n - jbase);
-        for (int k = 0; k < nj; ++k) {
-            const float xk = bcast(xj, k), yk = bcast(yj, k), zk = bcast(zj, k);
-            const float qk = bcast(qj, k), Rk = bcast(Rj, k), iRk = bcast(iRj, k);
-            const float hsk = bcast(hsj, k), sek = bcast(sej, k);
-            const int lk = jbase + k;
+        float e_c = 0.0f, e_g = 0.0f, e_lj = 0.0f;
+        for (int k = 0; k < 64; ++k) {
+            const int m = (lane + k + 1) & 63;
+            const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
+            const int lj = g.jbase + m;
+            const bool jok = m < g.nj;
             float cx = 0.0f, cy = 0.0f, cz = 0.0f, cR = 0.0f, cq = 0.0f;
 #pragma unroll
             for (int u = 0; u < NI; ++u) {
-                const float dx = xk - xi[u], dy = yk - yi[u], dz = zk - zi[u];
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const bool valid = li[u] < lk;
-                const float rinv = frsq(r2);
-                const float rinv2 = rinv * rinv;
-                const float qq = qi[u] * qk;
-                const float ec = ke_in * qq * rinv;
-                const float D = 0.25f * r2 * (iRi[u] * iRk);
-                const float ex = fexp_neg(D);
-                const float f2 = __builtin_fmaf(Ri[u] * Rk, ex, r2);
-                const float finv = frsq(f2);
-                const float finv2 = finv * finv;
-                const float egb = -ketau * qq * finv;
-                const float sg = hsi[u] + hsk;
-                const float s2 = sg * sg * rinv2;
-                const float s6 = s2 * s2 * s2;
-                const float s12 = s6 * s6;
-                const float e4 = sei[u] * sek;
-                const float elj = e4 * (s12 - s6);
-                float fs = -(ec + 6.0f * e4 * (2.0f * s12 - s6)) * rinv2
-                           - egb * finv2 * (1.0f - 0.25f * ex);
-                float gR = -0.5f * egb * finv2 * ex * (1.0f + D);
-                fs = sel(valid, fs);
-                gR = sel(valid, gR);
-                e_c += sel(valid, ec);
-                e_gb += sel(valid, egb);
-                e_lj += sel(valid, elj);
-                const float fx = fs * dx, fy = fs * dy, fz = fs * dz;
-                fxi[u] += fx; fyi[u] += fy; fzi[u] += fz;
-                cx -= fx; cy -= fy; cz -= fz;
-                dRi[u] += gR * Rk;
-                cR += gR * Ri[u];
-                if (GQ) {
-                    const float w = sel(valid, ke_in * rinv - ketau * finv);
-                    dqi[u] += w * qk;
-                    cq += w * qi[u];
+                if (u < g.u_lim) {
+                    const bool valid = jok && li[u] < lj;
+                    const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float rinv = valid ? frsq(r2) : 0.0f;
+                    const float rinv2 = rinv * rinv;
+                    const float qq = qi[u] * p0.w;
+                    const float ec = qq * rinv;
+                    const float D2 = r2 * (Li[u] * p1.y);          // D log2(e)
+                    const float ex = __builtin_amdgcn_exp2f(-D2);   // exp(-D)
+                    const float f2 = __builtin_fmaf(Ri[u] * p1.x, ex, r2);
+                    const float finv = valid ? frsq(f2) : 0.0f;
+                    const float eg = qq * finv;
+                    const float t = eg * finv * finv;               // qq / f^3
+                    const float sgr = (hsi[u] + p1.z) * rinv;
+                    const float s2 = sgr * sgr;
+                    const float s6 = s2 * s2 * s2;
+                    const float A = (sei[u] * p1.w) * s6;           // 4 eps_ij s^6
+                    const float B = A * s6;                         // 4 eps_ij s^12
+                    const float elj = B - A;
+                    const float uu = __builtin_fmaf(6.0f, B + elj, ec);
+                    const float w = __builtin_fmaf(ex, wq, taup);   // tau' (1 - exp(-D)/4)
+                    const float fs = __builtin_fmaf(-uu, rinv2, t * w);
+                    const float gR = t * ex * __builtin_fmaf(D2, hl, 0.5f);
+                    e_c += ec;
+                    e_g += eg;
+                    e_lj += elj;
+                    fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
+                    fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
+                    fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
+                    cx = __builtin_fmaf(-fs, dx, cx);
+                    cy = __builtin_fmaf(-fs, dy, cy);
+                    cz = __builtin_fmaf(-fs, dz, cz);
+                    dRi[u] = __builtin_fmaf(gR, p1.x, dRi[u]);
+                    cR = __builtin_fmaf(gR, Ri[u], cR);
+                    if (GQ) {
+                        const float wqq = __builtin_fmaf(-taup, finv, rinv);
+                        dqi[u] = __builtin_fmaf(wqq, p0.w, dqi[u]);
+                        cq = __builtin_fmaf(wqq, qi[u], cq);
+                    }
                 }
             }
-            const float tx = wave_sum(cx), ty = wave_sum(cy), tz = wave_sum(cz);
-            const float tR = wave_sum(cR);
-            const bool mine = lane == k;
-            fxj += mine ? tx : 0.0f;
-            fyj += mine ? ty : 0.0f;
-            fzj += mine ? tz : 0.0f;
-            dRj += mine ? tR : 0.0f;
-            if (GQ) {
-                const float tq = wave_sum(cq);
-                dqj += mine ? tq : 0.0f;
-            }
+            fxj = rot_add(fxj, cx);
+            fyj = rot_add(fyj, cy);
+            fzj = rot_add(fzj, cz);
+            dRj = rot_add(dRj, cR);
+            if (GQ) dqj = rot_add(dqj, cq);
         }
+        wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            if (li[u] < n) {
-                const int a = a0 + li[u];
+            if (li[u] < g.n) {
+                const int a = g.a0 + li[u];
                 atomic_add_fx(&force_fx[a], to_fixed(fxi[u], FX_FORCE, err));
                 atomic_add_fx(&force_fx[ntot + a], to_fixed(fyi[u], FX_FORCE, err));
                 atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzi[u], FX_FORCE, err));
-                atomic_add_fx(&dEdR_fx[a], to_fixed(dRi[u], FX_FORCE, err));
-                if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed(dqi[u], FX_FORCE, err));
+                atomic_add_fx(&dEdR_fx[a], to_fixed((double)dRi[u] * taup, FX_FORCE, err));
+                if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)dqi[u] * sq_ke_in, FX_FORCE, err));
             }
         }
-        if (lj < n) {
-            atomic_add_fx(&force_fx[ja], to_fixed(fxj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[ntot + ja], to_fixed(fyj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[2 * ntot + ja], to_fixed(fzj, FX_FORCE, err));
-            atomic_add_fx(&dEdR_fx[ja], to_fixed(dRj, FX_FORCE, err));
-            if (GQ) atomic_add_fx(&dEdq_fx[ja], to_fixed(dqj, FX_FORCE, err));
+        if (g.jbase + lane < g.n) {
+            const int a = g.a0 + g.jbase + lane;
+            atomic_add_fx(&force_fx[a], to_fixed(fxj, FX_FORCE, err));
+            atomic_add_fx(&force_fx[ntot + a], to_fixed(fyj, FX_FORCE, err));
+            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzj, FX_FORCE, err));
+            atomic_add_fx(&dEdR_fx[a], to_fixed((double)dRj * taup, FX_FORCE, err));
+            if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)dqj * sq_ke_in, FX_FORCE, err));
         }
-        const double sgb = wave_sum_d((double)e_gb);
+        const double sgb = wave_sum_d(-(double)taup * (double)e_g);
         const double sc = wave_sum_d((double)e_c);
         const double slj = wave_sum_d((double)e_lj);
         if (lane == 0) {
-            atomic_add_fx(&energy_fx[4 * rep + 0], to_fixed(sgb, FX_ENERGY, err));
-            atomic_add_fx(&energy_fx[4 * rep + 1], to_fixed(sc, FX_ENERGY, err));
-            atomic_add_fx(&energy_fx[4 * rep + 2], to_fixed(slj, FX_ENERGY, err));
+            atomic_add_fx(&energy_fx[4 * g.rep + 0], to_fixed(sgb, FX_ENERGY, err));
+            atomic_add_fx(&energy_fx[4 * g.rep + 1], to_fixed(sc, FX_ENERGY, err));
+            atomic_add_fx(&energy_fx[4 * g.rep + 2], to_fixed(slj, FX_ENERGY, err));
         }
     }
 }
 
 // ------------------------------------------------- chain rule through psi
 // F_i += g (x_j - x_i)/r,  g = c_i dh(r; rt_i, s_j)/dr + c_j dh(r; rt_j, s_i)/dr,
-// c = (dE/dR)(dR/dpsi)(rho~/2).  With RHO also the pair part of dE/drho:
+// c = (dE/dR)(dR/dpsi)(rho~/2).  Distant spheres: dh/dr = -(s^3/r^5) Q(s^2/r^2),
+// so g/r = -(c_i s_j^3 Q_ij + c_j s_i^3 Q_ji) / r^6.
+// With RHO also the pair part of dE/drho:
 //   i: c_i dh_ij/drt + S_i c_j dh_ji/ds,   j: c_j dh_ji/drt + S_j c_i dh_ij/ds.
+// j tile in LDS: {x, y, z, c}, {rt, s, m, sx}, {s^2, s^3, S, -}.
 template <int NI, bool RHO>
 __global__ __launch_bounds__(256) void k_chain_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
@@ -234,87 +311,103 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     const float* __restrict__ screen, const float* __restrict__ cc, float offset,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdrho_fx, uint32_t* __restrict__ err)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ float4 lds[MAXW][3][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int stride = gridDim.x * (blockDim.x >> 6);
+    const float ixmax = 1.0f / HCT_FAR_XMAX;
     for (int it = logical_wave(); it < n_items; it += stride) {
-        const int2 wi = items[it];
-        const int rep = wi.x, IB = wi.y >> 16, J = wi.y & 0xFFFF;
-        const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
-        float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], ci[NI], Si[NI];
+        const ItemGeom g = item_geom<NI>(items[it], atom_off);
+        float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], ci[NI], Si[NI], mi[NI], sxi[NI], s2i[NI], s3i[NI];
         float fxi[NI], fyi[NI], fzi[NI], dri[NI];
         int li[NI];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            li[u] = IB * 64 * NI + u * 64 + lane;
-            const int a = a0 + min(li[u], n - 1);
+            li[u] = g.ibase + u * 64 + lane;
+            const int a = g.a0 + min(li[u], g.n - 1);
             xi[u] = xyz[a]; yi[u] = xyz[ntot + a]; zi[u] = xyz[2 * ntot + a];
             rti[u] = rho[a] - offset;
             Si[u] = screen[a];
             si[u] = Si[u] * rti[u];
             ci[u] = cc[a];
+            mi[u] = fmaxf(rti[u], si[u]);
+            sxi[u] = si[u] * ixmax;
+            s2i[u] = si[u] * si[u];
+            s3i[u] = s2i[u] * si[u];
             fxi[u] = fyi[u] = fzi[u] = dri[u] = 0.0f;
         }
-        const int jbase = J * 64;
-        const int lj = jbase + lane;
-        const int ja = a0 + min(lj, n - 1);
-        const float xj = xyz[ja], yj = xyz[ntot + ja], zj = xyz[2 * ntot + ja];
-        const float rtj = rho[ja] - offset, Sj = screen[ja], sj = Sj * rtj, cjv = cc[ja];
+        {
+            const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
+            const float rt = rho[ja] - offset, S = screen[ja], s = S * rt;
+            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], cc[ja]);
+            lds[wv][1][lane] = make_float4(rt, s, fmaxf(rt, s), s * ixmax);
+            lds[wv][2][lane] = make_float4(s * s, s * s * s, S, 0.0f);
+        }
+        wave_lds_fence();
         float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, drj = 0.0f;
-        const int nj = min(64, n - jbase);
-        for (int k = 0; k < nj; ++k) {
-            const float xk = bcast(xj, k), yk = bcast(yj, k), zk = bcast(zj, k);
-            const float rtk = bcast(rtj, k), sk = bcast(sj, k), ck = bcast(cjv, k);
-            const float Sk = RHO ? bcast(Sj, k) : 0.0f;
-            const int lk = jbase + k;
+        for (int k = 0; k < 64; ++k) {
+            const int m = (lane + k + 1) & 63;
+            const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m], p2 = lds[wv][2][m];
+            const int lj = g.jbase + m;
+            const bool jok = m < g.nj;
             float cx = 0.0f, cy = 0.0f, cz = 0.0f, cr = 0.0f;
 #pragma unroll
             for (int u = 0; u < NI; ++u) {
-                const float dx = xk - xi[u], dy = yk - yi[u], dz = zk - zi[u];
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const bool valid = li[u] < lk;
-                const float rinv = frsq(r2);
-                const float r = r2 * rinv;
-                float g;
-                if (RHO) {
-                    float dr_ij, drt_ij, ds_ij, dr_ji, drt_ji, ds_ji;
-                    hct_grad3(r, rinv, rti[u], sk, dr_ij, drt_ij, ds_ij);
-                    hct_grad3(r, rinv, rtk, si[u], dr_ji, drt_ji, ds_ji);
-                    g = ci[u] * dr_ij + ck * dr_ji;
-                    dri[u] += sel(valid, ci[u] * drt_ij + Si[u] * ck * ds_ji);
-                    cr += sel(valid, ck * drt_ji + Sk * ci[u] * ds_ij);
-                } else {
-                    g = ci[u] * hct_dr(r, rinv, rti[u], sk) + ck * hct_dr(r, rinv, rtk, si[u]);
+                if (u < g.u_lim) {
+                    const bool valid = jok && li[u] < lj;
+                    const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    r2 = valid ? r2 : FAR_R2;
+                    const float rinv = frsq(r2);
+                    const float r = r2 * rinv;
+                    const float rinv2 = rinv * rinv;
+                    float fs;
+                    if (!RHO) {
+                        const float Qij = poly_Q(p2.x * rinv2), Qji = poly_Q(s2i[u] * rinv2);
+                        const float G = __builtin_fmaf(p0.w * s3i[u], Qji, ci[u] * (p2.y * Qij));
+                        fs = -G * (rinv2 * rinv2 * rinv2);
+                        if (!both_far(r, mi[u], p1.z, sxi[u], p1.w)) {
+                            const float dij = (r + p1.y <= rti[u]) ? 0.0f : hct_dr_closed(r, rinv, rti[u], p1.y);
+                            const float dji = (r + si[u] <= p1.x) ? 0.0f : hct_dr_closed(r, rinv, p1.x, si[u]);
+                            fs = (ci[u] * dij + p0.w * dji) * rinv;
+                        }
+                    } else {
+                        float dr_ij, drt_ij, ds_ij, dr_ji, drt_ji, ds_ji;
+                        hct_grad3(r, rinv, rti[u], p1.y, dr_ij, drt_ij, ds_ij);
+                        hct_grad3(r, rinv, p1.x, si[u], dr_ji, drt_ji, ds_ji);
+                        fs = (ci[u] * dr_ij + p0.w * dr_ji) * rinv;
+                        dri[u] += ci[u] * drt_ij + Si[u] * p0.w * ds_ji;
+                        cr += p0.w * drt_ji + p2.z * ci[u] * ds_ij;
+                    }
+                    fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
+                    fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
+                    fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
+                    cx = __builtin_fmaf(-fs, dx, cx);
+                    cy = __builtin_fmaf(-fs, dy, cy);
+                    cz = __builtin_fmaf(-fs, dz, cz);
                 }
-                const float fs = sel(valid, g * rinv);
-                const float fx = fs * dx, fy = fs * dy, fz = fs * dz;
-                fxi[u] += fx; fyi[u] += fy; fzi[u] += fz;
-                cx -= fx; cy -= fy; cz -= fz;
             }
-            const float tx = wave_sum(cx), ty = wave_sum(cy), tz = wave_sum(cz);
-            const bool mine = lane == k;
-            fxj += mine ? tx : 0.0f;
-            fyj += mine ? ty : 0.0f;
-            fzj += mine ? tz : 0.0f;
-            if (RHO) {
-                const float tr = wave_sum(cr);
-                drj += mine ? tr : 0.0f;
-            }
+            fxj = rot_add(fxj, cx);
+            fyj = rot_add(fyj, cy);
+            fzj = rot_add(fzj, cz);
+            if (RHO) drj = rot_add(drj, cr);
         }
+        wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            if (li[u] < n) {
-                const int a = a0 + li[u];
+            if (li[u] < g.n) {
+                const int a = g.a0 + li[u];
                 atomic_add_fx(&force_fx[a], to_fixed(fxi[u], FX_FORCE, err));
                 atomic_add_fx(&force_fx[ntot + a], to_fixed(fyi[u], FX_FORCE, err));
                 atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzi[u], FX_FORCE, err));
                 if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(dri[u], FX_FORCE, err));
             }
         }
-        if (lj < n) {
-            atomic_add_fx(&force_fx[ja], to_fixed(fxj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[ntot + ja], to_fixed(fyj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[2 * ntot + ja], to_fixed(fzj, FX_FORCE, err));
-            if (RHO) atomic_add_fx(&dEdrho_fx[ja], to_fixed(drj, FX_FORCE, err));
+        if (g.jbase + lane < g.n) {
+            const int a = g.a0 + g.jbase + lane;
+            atomic_add_fx(&force_fx[a], to_fixed(fxj, FX_FORCE, err));
+            atomic_add_fx(&force_fx[ntot + a], to_fixed(fyj, FX_FORCE, err));
+            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzj, FX_FORCE, err));
+            if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(drj, FX_FORCE, err));
         }
     }
 }
@@ -368,9 +461,10 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     const PairList& L = list_for(c, c->ni_energy);
     if (L.n_items == 0) return hipSuccess;
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
-    const GBConstH k = make_const(c->prm);
+    const float sq = (float)sqrt(c->prm.k_e / c->prm.eps_in);
+    const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
 #define GBR_EN(NI, GQ) hipLaunchKernelGGL((k_energy_pair<NI, GQ>), grid, block, 0, s, L.items, \
-        L.n_items, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, k.ke, k.ke_in, k.tau, force_fx, \
+        L.n_items, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, force_fx, \
         c->dEdR_fx, energy_fx, dEdq_fx, c->err)
     const bool gq = dEdq_fx != nullptr;
     switch (L.ni) {
