@@ -171,8 +171,10 @@ int gbr_set_launch(gbr_ctx* ctx, int32_t waves_per_group, int32_t groups_per_cu)
 int gbr_set_blocking(gbr_ctx* ctx, int32_t ni_born, int32_t ni_energy, int32_t ni_chain);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
- * kernel of each GBR_K_* kind while enabled (eager launches only). */
-int gbr_set_timing(gbr_ctx* ctx, int32_t enable);
+ * kernel of the GBR_K_* kinds whose bit (1 << kind) is set in kinds_mask
+ * (0 disables; eager launches only: md_step does not replay graphs while any
+ * kind is timed). */
+int gbr_set_timing(gbr_ctx* ctx, int32_t kinds_mask);
 /* Synchronizes; ms_out[k] = summed milliseconds, count_out[k] = launches, for
  * k < GBR_K_COUNT; then resets the accumulators. */
 int gbr_get_timing(gbr_ctx* ctx, double* ms_out, int64_t* count_out);

@@ -55,7 +55,7 @@ struct Timed {
     hipEvent_t stop = nullptr;
     Timed(gbr_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
         Timer& t = c->timer;
-        if (!t.enabled) return;
+        if (!(t.mask & (1 << kind_))) return;
         if (t.used + 2 > t.pool.size()) {
             size_t old = t.pool.size();
             t.pool.resize(old + 512);
@@ -358,9 +358,11 @@ int gbr_set_blocking(gbr_ctx* c, int32_t ni_born, int32_t ni_energy, int32_t ni_
     return GBR_OK;
 }
 
-int gbr_set_timing(gbr_ctx* c, int32_t enable) {
+int gbr_set_timing(gbr_ctx* c, int32_t kinds_mask) {
     if (int rc = check_ctx(c)) return rc;
-    c->timer.enabled = enable != 0;
+    if (kinds_mask < 0 || kinds_mask >= (1 << GBR_K_COUNT))
+        return fail(GBR_E_INVAL, "kinds_mask must be a subset of the GBR_K_* bits");
+    c->timer.mask = kinds_mask;
     return GBR_OK;
 }
 
@@ -561,7 +563,7 @@ int md_step(gbr_ctx* c, gbr_md_state* st, const gbr_md_params* pr, uint64_t seed
         e = launch_md_last(c, a, 0, s);
         if (e != hipSuccess) return hip_fail(e, "md init");
     }
-    const bool use_graph = (flags & GBR_MD_GRAPH) != 0 && !c->timer.enabled;
+    const bool use_graph = (flags & GBR_MD_GRAPH) != 0 && c->timer.mask == 0;
     uint64_t key = use_graph ? hash_args(a) : 0;
     for (int32_t k = 0; k < n_steps; ++k) {
         const uint64_t n = step0 + (uint64_t)k;

@@ -10,7 +10,6 @@
 #include "hct_poly.h"
 
 #define GBR_WAVE 64
-#define GBR_TILE 64          // atoms per pair tile (one per lane)
 
 namespace gbr {
 
@@ -25,15 +24,6 @@ constexpr double INV_FX_FORCE = 1.0 / FX_FORCE;
 constexpr double INV_FX_ENERGY = 1.0 / FX_ENERGY;
 
 enum Stream : uint32_t { STREAM_O = 1, STREAM_MCPH = 2, STREAM_MCRED = 3, STREAM_EX = 4 };
-
-// Per-launch constants of the GB model (FP32 copies for the pair kernels).
-struct GBConst {
-    float ke;        // k_e
-    float ke_in;     // k_e / eps_in
-    float tau;       // 1/eps_in - 1/eps_out
-    float offset;    // dielectric offset
-    double ke_d, ke_in_d, tau_d, offset_d, alpha, beta, gamma;
-};
 
 // ------------------------------------------------------------ fixed point
 __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t bits) {
@@ -63,40 +53,11 @@ __device__ __forceinline__ double from_fixed(int64_t v, double inv_scale) {
 }
 
 // -------------------------------------------------------- wave reductions
-// DPP-based sum over the 64 lanes of a wavefront; the total is valid in lane 63.
-// Every lane must be active.
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                  CTRL, ROW_MASK, 0xF, true));
-}
-
-__device__ __forceinline__ float wave_sum_to_63(float v) {
-    v += dpp_f<0xB1>(v);        // quad_perm [1,0,3,2]
-    v += dpp_f<0x4E>(v);        // quad_perm [2,3,0,1]
-    v += dpp_f<0x124>(v);       // row_ror:4
-    v += dpp_f<0x128>(v);       // row_ror:8  -> every lane holds its row's sum
-    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-    v = wave_sum_to_63(v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
-
 __device__ __forceinline__ double wave_sum_d(double v) {
     // doubles: butterfly through shuffles (used only once per tile)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, GBR_WAVE);
     return v;
 }
-
-__device__ __forceinline__ float bcast(float v, int lane) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
-}
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // -------------------------------------------------- Philox4x32-10 (SC'11)
 struct U4 { uint32_t x, y, z, w; };
@@ -144,8 +105,9 @@ __device__ __forceinline__ void normal2(U4 w, double& n0, double& n1) {
 // radius rt: twice the integral over shells t >= rt of (covered fraction)/t^2.
 //  - sphere inside the atom (r + s <= rt): 0
 //  - distant sphere (r - s >= rt, s/r <= HCT_FAR_XMAX): (x^3/r) G(x^2), x = s/r
+//    (evaluated in the pair kernels)
 //  - otherwise the closed form with L = max(rt, |r - s|), U = r + s, plus the
-//    engulfing term when rt < s - r.
+//    engulfing term when rt < s - r (hct_closed).
 __device__ __forceinline__ float poly_G(float y) {
     float p = hct_G_coef[HCT_G_DEG];
 #pragma unroll
@@ -165,11 +127,6 @@ __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x)
 __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ __forceinline__ float fexp_neg(float x) { return __builtin_amdgcn_exp2f(-x * 1.4426950408889634f); }
 
-struct HctNear {
-    float L, U, iL, iU;
-    bool engulfed;
-};
-
 __device__ __forceinline__ float hct_closed(float r, float rinv, float rt, float s) {
     float U = r + s;
     float rms = r - s;
@@ -181,18 +138,7 @@ __device__ __forceinline__ float hct_closed(float r, float rinv, float rt, float
     return h;
 }
 
-__device__ __forceinline__ float hct_h(float r, float rinv, float rt, float s) {
-    float x = s * rinv;
-    float y = x * x;
-    float h = x * y * rinv * poly_G(y);
-    bool far = (r - s >= rt) && (x <= HCT_FAR_XMAX);
-    if (!far) {
-        h = (r + s <= rt) ? 0.0f : hct_closed(r, rinv, rt, s);
-    }
-    return h;
-}
-
-// dh/dr.  Distant sphere: -(x^3/r^2) Q(x^2).  Otherwise
+// dh/dr.  Distant sphere: -(x^3/r^2) Q(x^2) (in the pair kernels).  Otherwise
 //   dh/dr = [ (r^2 + s^2)(1/U^2 - 1/L^2)/2 + ln(U/L) ] / (2 r^2)
 // (the boundary terms of the shell integral vanish or cancel in every branch).
 __device__ __forceinline__ float hct_dr_closed(float r, float rinv, float rt, float s) {
@@ -201,17 +147,6 @@ __device__ __forceinline__ float hct_dr_closed(float r, float rinv, float rt, fl
     float iL = frcp(L), iU = frcp(U);
     float a = (r * r + s * s) * (iU * iU - iL * iL) * 0.5f - flog(L * iU);
     return a * 0.5f * rinv * rinv;
-}
-
-__device__ __forceinline__ float hct_dr(float r, float rinv, float rt, float s) {
-    float x = s * rinv;
-    float y = x * x;
-    float d = -(x * y * rinv * rinv) * poly_Q(y);
-    bool far = (r - s >= rt) && (x <= HCT_FAR_XMAX);
-    if (!far) {
-        d = (r + s <= rt) ? 0.0f : hct_dr_closed(r, rinv, rt, s);
-    }
-    return d;
 }
 
 // All three partials (for the radius adjoint).

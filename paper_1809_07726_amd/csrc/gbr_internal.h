@@ -25,7 +25,7 @@ struct LaunchShape {
 };
 
 struct Timer {
-    bool enabled = false;
+    int32_t mask = 0;               // bit k: time kernels of kind k
     std::vector<hipEvent_t> pool;   // pairs of events
     std::vector<int> kind;          // kind of each recorded pair
     size_t used = 0;

@@ -85,7 +85,8 @@ __device__ __forceinline__ bool both_far(float r, float mi, float mj, float sxi,
 }
 
 // ------------------------------------------------------------- descreening
-// j tile in LDS: {x, y, z, s}, {rt, m, sx, -}
+// Distant spheres: h = (x^3/r) G(x^2) with x = s/r, i.e. h = s^3 r^-4 G(s^2 r^-2).
+// j tile in LDS: {x, y, z, s^2}, {rt, m, sx, s^3}
 template <int NI>
 __global__ __launch_bounds__(256) void k_born_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
     const float ixmax = 1.0f / HCT_FAR_XMAX;
     for (int it = logical_wave(); it < n_items; it += stride) {
         const ItemGeom g = item_geom<NI>(items[it], atom_off);
-        float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], mi[NI], sxi[NI], acc[NI];
+        float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], s2i[NI], s3i[NI], mi[NI], sxi[NI], acc[NI];
         int li[NI];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
@@ -108,6 +109,8 @@ __global__ __launch_bounds__(256) void k_born_pair(
             xi[u] = xyz[a]; yi[u] = xyz[ntot + a]; zi[u] = xyz[2 * ntot + a];
             rti[u] = rho[a] - offset;
             si[u] = screen[a] * rti[u];
+            s2i[u] = si[u] * si[u];
+            s3i[u] = s2i[u] * si[u];
             mi[u] = fmaxf(rti[u], si[u]);
             sxi[u] = si[u] * ixmax;
             acc[u] = 0.0f;
@@ -115,8 +118,8 @@ __global__ __launch_bounds__(256) void k_born_pair(
         {
             const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
             const float rt = rho[ja] - offset, s = screen[ja] * rt;
-            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s);
-            lds[wv][1][lane] = make_float4(rt, fmaxf(rt, s), s * ixmax, 0.0f);
+            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s * s);
+            lds[wv][1][lane] = make_float4(rt, fmaxf(rt, s), s * ixmax, s * s * s);
         }
         wave_lds_fence();
         float accj = 0.0f;
@@ -133,14 +136,14 @@ __global__ __launch_bounds__(256) void k_born_pair(
                     float r2 = dx * dx + dy * dy + dz * dz;
                     r2 = (jok && li[u] < lj) ? r2 : FAR_R2;
                     const float rinv = frsq(r2);
+                    const float rinv2 = rinv * rinv;
+                    const float rinv4 = rinv2 * rinv2;
+                    float hij = (p1.w * rinv4) * poly_G(p0.w * rinv2);
+                    float hji = (s3i[u] * rinv4) * poly_G(s2i[u] * rinv2);
                     const float r = r2 * rinv;
-                    // distant-sphere forms, x = s/r:  h = (x^3/r) G(x^2)
-                    const float xij = p0.w * rinv, yij = xij * xij;
-                    const float xji = si[u] * rinv, yji = xji * xji;
-                    float hij = xij * yij * rinv * poly_G(yij);
-                    float hji = xji * yji * rinv * poly_G(yji);
                     if (!both_far(r, mi[u], p1.y, sxi[u], p1.z)) {
-                        hij = (r + p0.w <= rti[u]) ? 0.0f : hct_closed(r, rinv, rti[u], p0.w);
+                        const float sj = p1.z * HCT_FAR_XMAX;
+                        hij = (r + sj <= rti[u]) ? 0.0f : hct_closed(r, rinv, rti[u], sj);
                         hji = (r + si[u] <= p1.x) ? 0.0f : hct_closed(r, rinv, p1.x, si[u]);
                     }
                     acc[u] += hij;

@@ -55,8 +55,15 @@ class Context:
     def set_blocking(self, ni_born, ni_energy, ni_chain):
         check(A.lib.gbr_set_blocking(self.h, ni_born, ni_energy, ni_chain))
 
-    def set_timing(self, on: bool):
-        check(A.lib.gbr_set_timing(self.h, int(bool(on))))
+    def set_timing(self, on, kinds=None):
+        """Time kernels with HIP events: all kinds when on is True, or only the
+        named kinds (see _capi.KERNEL_KINDS)."""
+        mask = 0
+        if on:
+            names = kinds or A.KERNEL_KINDS
+            for k in names:
+                mask |= 1 << A.KERNEL_KINDS.index(k)
+        check(A.lib.gbr_set_timing(self.h, mask))
 
     def get_timing(self):
         ms = (C.c_double * A.K_COUNT)()

@@ -1,0 +1,85 @@
+"""Autotuner for the pair kernels.
+
+Times the three pair passes (descreening, energy, chain rule) on the caller's
+own batch for every register blocking (i atoms per lane: 1, 2, 4, 8) and a set
+of launch shapes (wavefronts per workgroup x workgroups per CU of the
+persistent grid), using the library's HIP-event kernel timers, and installs
+the fastest combination in the context: per pass the fastest blocking, and the
+launch shape whose summed pass time is lowest.  Results can be cached in a JSON
+file keyed by the device architecture and the batch's replica sizes.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import torch
+
+PASSES = ("born_pair", "energy_pair", "chain_pair")
+SHAPES = ((4, 8), (4, 16), (4, 32), (2, 16))
+BLOCKINGS = (1, 2, 4, 8)
+
+
+def batch_key(ctx) -> str:
+    arch = torch.cuda.get_device_properties(ctx.device).gcnArchName.split(":")[0]
+    sizes = np.diff(ctx.atom_off)
+    h = hashlib.sha256(np.ascontiguousarray(sizes.astype(np.int32)).tobytes()).hexdigest()[:16]
+    return f"{arch}:{ctx.n_rep}:{h}"
+
+
+def _time_eval(ctx, t, reps):
+    R, dR, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"], want_psi=False)
+    ctx.energy_forces(t["xyz"], t["q"], t["rho"], t["screen"], t["sigma"], t["eps"], R, dR)
+    torch.cuda.synchronize()
+    ctx.set_timing(True, PASSES)
+    ctx.get_timing()
+    for _ in range(reps):
+        R, dR, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"], want_psi=False)
+        ctx.energy_forces(t["xyz"], t["q"], t["rho"], t["screen"], t["sigma"], t["eps"], R, dR)
+    tm = ctx.get_timing()
+    ctx.set_timing(False)
+    return {k: tm[k][0] / max(tm[k][1], 1) for k in PASSES}
+
+
+def autotune(ctx, t: dict, reps: int = 3, shapes=SHAPES, blockings=BLOCKINGS,
+             cache: str | None = None) -> dict:
+    """Tune ctx for the inputs in t (the DeviceBatch tensors); returns
+    {"shape": (wpg, gpc), "blocking": (ni_born, ni_energy, ni_chain),
+     "ms": {pass: ms}, "table": [...]}."""
+    key = batch_key(ctx)
+    if cache and os.path.exists(cache):
+        store = json.load(open(cache))
+        if key in store:
+            best = store[key]
+            ctx.set_launch(*best["shape"])
+            ctx.set_blocking(*best["blocking"])
+            best["cached"] = True
+            return best
+    table = []
+    for shape in shapes:
+        ctx.set_launch(*shape)
+        for ni in blockings:
+            ctx.set_blocking(ni, ni, ni)
+            ms = _time_eval(ctx, t, reps)
+            table.append({"shape": list(shape), "ni": ni, **ms})
+    best = None
+    for shape in shapes:
+        rows = [r for r in table if tuple(r["shape"]) == tuple(shape)]
+        pick = {p: min(rows, key=lambda r: r[p]) for p in PASSES}
+        total = sum(pick[p][p] for p in PASSES)
+        if best is None or total < best["total_ms"]:
+            best = {"shape": list(shape), "blocking": [pick[p]["ni"] for p in PASSES],
+                    "ms": {p: pick[p][p] for p in PASSES}, "total_ms": total}
+    ctx.set_launch(*best["shape"])
+    ctx.set_blocking(*best["blocking"])
+    best["table"] = table
+    best["key"] = key
+    if cache:
+        store = json.load(open(cache)) if os.path.exists(cache) else {}
+        store[key] = {k: best[k] for k in ("shape", "blocking", "ms", "total_ms")}
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as fh:
+            json.dump(store, fh, indent=1)
+    return best

@@ -1,0 +1,125 @@
+"""The adjoint behind torch.autograd (dE/dx, dE/dq, dE/drho) against the FP64
+oracle's analytic gradient, and the batched evaluation at the full workload
+sizes: sampled replicas against the oracle, properties that hold at any size
+for the rest (finite energies, vanishing net force, run-to-run identity)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import E_TOL, F_TOL, FX_F, gpu_eval, rms_rel, soa_to_aos, to_dev
+from paper_1809_07726_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_check(b, g, reps):
+    off = b["atom_off"]
+    for r in reps:
+        a, c = off[r], off[r + 1]
+        Eo, gx, _, _ = oracle.gradient(b["xyz"][a:c], b["q"][a:c], b["rho"][a:c], b["screen"][a:c],
+                                       b["sigma"][a:c], b["eps"][a:c])
+        assert abs(g["E"][r, 4] - Eo.sum()) <= E_TOL * abs(Eo.sum()), (r, g["E"][r], Eo)
+        assert abs(g["E"][r, 0] - Eo[0]) <= E_TOL * abs(Eo[0])
+        assert rms_rel(g["F"][a:c], -gx) < F_TOL, r
+
+
+def _any_size_properties(b, g):
+    off = b["atom_off"]
+    assert np.all(np.isfinite(g["E"]))
+    for r in range(off.size - 1):
+        F = g["F"][off[r]:off[r + 1]]
+        assert np.abs(F.sum(0)).max() <= 2e-8 * np.abs(F).sum() + 1e-9
+
+
+def test_autograd_matches_oracle_gradient():
+    """Two 4,096-atom replicas with independent jitter (the differentiation
+    workload's shape); upstream gradient differs per replica."""
+    from paper_1809_07726_amd.gb import Context, gb_energy
+    b = synth.make_config(3, n_rep=2)
+    d = to_dev(b)
+    t = d.t
+    ctx = Context(b["atom_off"])
+    x = t["xyz"].clone().requires_grad_(True)
+    q = t["q"].clone().requires_grad_(True)
+    rho = t["rho"].clone().requires_grad_(True)
+    E = gb_energy(x, q, rho, t["screen"], t["sigma"], t["eps"], ctx)
+    w = torch.tensor([0.7, -1.3], dtype=torch.float64, device="cuda")
+    (E * w).sum().backward()
+    ctx.check()
+    N = ctx.n_atoms
+    gx = soa_to_aos(x.grad.cpu().numpy(), N)
+    gq = q.grad.cpu().double().numpy()
+    gr = rho.grad.cpu().double().numpy()
+    Eg = E.detach().cpu().numpy()
+    off = b["atom_off"]
+    wn = w.cpu().numpy()
+    for r in range(2):
+        a, c = off[r], off[r + 1]
+        Eo, ox, oq, orr = oracle.gradient(b["xyz"][a:c], b["q"][a:c], b["rho"][a:c], b["screen"][a:c],
+                                          b["sigma"][a:c], b["eps"][a:c])
+        assert abs(Eg[r] - Eo.sum()) <= E_TOL * abs(Eo.sum())
+        assert rms_rel(gx[a:c], wn[r] * ox) < F_TOL
+        assert rms_rel(gq[a:c], wn[r] * oq) < F_TOL
+        assert rms_rel(gr[a:c], wn[r] * orr) < F_TOL
+    ctx.close()
+
+
+def test_autograd_rejects_non_differentiable_inputs():
+    from paper_1809_07726_amd.gb import Context, gb_energy
+    b = synth.make_config(0, n_atoms=64)
+    d = to_dev(b)
+    t = d.t
+    ctx = Context(b["atom_off"])
+    scr = t["screen"].clone().requires_grad_(True)
+    with pytest.raises(ValueError):
+        gb_energy(t["xyz"], t["q"], t["rho"], scr, t["sigma"], t["eps"], ctx)
+    ctx.close()
+
+
+def test_uneven_batch_reduced():
+    """The uneven workload's structure (log-uniform sizes, sites every ~200
+    atoms, 4 pH replicas per system) at sizes the oracle finishes quickly."""
+    b = synth.make_config(4, n_systems=6, n_atoms=2500)
+    g = gpu_eval(b)
+    _sample_check(b, g, range(b["n_rep"]))
+
+
+def test_full_size_e_ph_t_batch_sampled():
+    """192 x 1,024 (the benchmarked batch) in one launch per pass; three
+    replicas checked element by element against the oracle."""
+    b = synth.make_config(2, per_replica_jitter=True)
+    g = gpu_eval(b)
+    _sample_check(b, g, [0, 95, 191])
+    _any_size_properties(b, g)
+
+
+def test_full_size_e_ph_batch_sampled():
+    b = synth.make_config(1, per_replica_jitter=True)
+    g = gpu_eval(b)
+    _sample_check(b, g, [0, 47])
+    _any_size_properties(b, g)
+
+
+def test_full_size_gradient_batch_sampled():
+    b = synth.make_config(3)
+    g = gpu_eval(b)
+    _sample_check(b, g, [5])
+    _any_size_properties(b, g)
+
+
+def test_full_size_uneven_batch_sampled_and_deterministic():
+    """64 systems of 500..20,000 atoms x 4 replicas: the smallest system's
+    replicas against the oracle; all replicas finite, force-balanced and
+    identical on a second run."""
+    b = synth.make_config(4)
+    g1 = gpu_eval(b)
+    sizes = np.diff(b["atom_off"])
+    r_small = int(np.argmin(sizes))
+    _sample_check(b, g1, [r_small])
+    _any_size_properties(b, g1)
+    g2 = gpu_eval(b)
+    assert np.array_equal(g1["F_fx"], g2["F_fx"]) and np.array_equal(g1["E_fx"], g2["E_fx"])
+    # replicas of one system share coordinates: identical energies across its 4 replicas
+    E = g1["E"][:, 4].reshape(-1, 4)
+    assert np.all(E == E[:, :1])
