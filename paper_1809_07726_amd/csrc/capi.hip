@@ -162,8 +162,7 @@ int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, hipStream_t s) {
 
 // The launches of one MD step (kind bit 0: MC attempts, bit 1: exchange attempt).
 int md_one_step(gbr_ctx* c, const MDArgs& a, int kind, hipStream_t s) {
-    hipError_t e = launch_step_begin(c, s);
-    if (e != hipSuccess) return hip_fail(e, "step begin");
+    hipError_t e;
     {
         Timed t(c, GBR_K_PER_ATOM, s);
         e = launch_md_first(c, a, s);
@@ -590,6 +589,8 @@ int md_step(gbr_ctx* c, gbr_md_state* st, const gbr_md_params* pr, uint64_t seed
         }
         GBR_HIP(hipGraphLaunch(c->graph[kind], s));
     }
+    e = launch_ke_out(c, st->ke, s);
+    if (e != hipSuccess) return hip_fail(e, "kinetic energy");
     return GBR_OK;
 }
 

@@ -134,7 +134,8 @@ __device__ __forceinline__ float hct_closed(float r, float rinv, float rt, float
     float iL = frcp(L), iU = frcp(U);
     float h = (iL - iU) + (iU * iU - iL * iL) * ((r * r - s * s) * 0.25f * rinv)
             + 0.5f * rinv * flog(L * iU);
-    if (rt < -rms) h += 2.0f * (frcp(rt) - iL);
+    // engulfed: + 2 (1/rt - 1/L), written with one reciprocal of the pair's rt L
+    if (rt < -rms) h += 2.0f * (L - rt) * frcp(rt * L);
     return h;
 }
 

@@ -58,7 +58,7 @@ struct gbr_ctx {
     int32_t* ex_ne = nullptr;
     double* ex_eps = nullptr;
     float* ex_vscale = nullptr;
-    uint64_t* step = nullptr;        // [2] current step, next step
+    uint64_t* step = nullptr;        // [2] current step index (second word unused)
     uint32_t* err = nullptr;         // device error word
     gbr::Timer timer;
     // captured per-step graphs (plain, MC, EX, MC+EX)
@@ -105,10 +105,10 @@ struct MDArgs {
     gbr_md_params pr;
     uint64_t seed;
 };
-hipError_t launch_step_begin(const gbr_ctx* c, hipStream_t s);
 hipError_t launch_set_step(const gbr_ctx* c, uint64_t step0, hipStream_t s);
 hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, hipStream_t s);
 hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s);
+hipError_t launch_ke_out(const gbr_ctx* c, double* ke, hipStream_t s);
 hipError_t launch_mc(const gbr_ctx* c, const MDArgs& a, hipStream_t s);
 hipError_t launch_titration(const gbr_ctx* c, const float* xyz, const float* q, const float* R,
                             const gbr_sites& sites, const int32_t* cand, int32_t n_cand,

@@ -9,23 +9,21 @@ using namespace gbr;
 namespace {
 
 // ----------------------------------------------------------- step counter
-// step[0] = index of the step being executed, step[1] = index of the next one.
-__global__ void k_set_step(uint64_t* step, uint64_t step0) { step[1] = step0; }
-__global__ void k_step_begin(uint64_t* step) {
-    step[0] = step[1];
-    step[1] = step[1] + 1;
-}
+// step[0] = index n of the step being executed; one thread of the step's
+// k_md_last (a kernel that does not read it) advances it to n + 1.
+__global__ void k_set_step(uint64_t* step, uint64_t step0) { step[0] = step0; }
 
 // ------------------------------------------------------ B, A, O, A stages
 // v += dt/2 F/m;  x += dt/2 v;  v = c1 v + c2 sqrt(kT/m) xi;  x += dt/2 v.
-// Also clears the accumulators of the force evaluation that follows.
+// Also clears the accumulators of the force evaluation that follows, after
+// handing the previous step's kinetic energy to ke (may be NULL).
 __global__ __launch_bounds__(256) void k_md_first(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
     const uint64_t* __restrict__ step, uint64_t seed, double hdt, double c1, double c2,
     const float* __restrict__ mass, const double* __restrict__ T_vals,
     const int32_t* __restrict__ target_idx, float* __restrict__ xyz, float* __restrict__ v,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ psi_fx,
-    int64_t* __restrict__ dEdR_fx, int64_t* __restrict__ ke_fx)
+    int64_t* __restrict__ dEdR_fx, int64_t* __restrict__ ke_fx, double* __restrict__ ke)
 {
     const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
@@ -35,7 +33,10 @@ __global__ __launch_bounds__(256) void k_md_first(
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
     const int li = tl.y * 64 + lane;
     if (tl.y == 0 && lane < 4) energy_fx[4 * rep + lane] = 0;
-    if (tl.y == 0 && lane == 0) ke_fx[rep] = 0;
+    if (tl.y == 0 && lane == 0) {
+        if (ke) ke[rep] = from_fixed(ke_fx[rep], INV_FX_ENERGY);
+        ke_fx[rep] = 0;
+    }
     if (li >= n) return;
     const int a = a0 + li;
     const uint64_t nstep = step[0];
@@ -62,13 +63,13 @@ __global__ __launch_bounds__(256) void k_md_first(
 }
 
 // Tether k |x - x0|^2 added to the forces and the replica's energy slot 3;
-// then (kick) v += dt/2 F/m and the kinetic energy.
+// then (kick) v += dt/2 F/m, the kinetic energy, and the step counter advances.
 __global__ __launch_bounds__(256) void k_md_last(
-    const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
-    double hdt, double k_t, const float* __restrict__ mass, const float* __restrict__ x0,
-    const float* __restrict__ xyz, float* __restrict__ v, int64_t* __restrict__ force_fx,
-    int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx, int kick,
-    uint32_t* __restrict__ err)
+    const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
+    int ntot, double hdt, double k_t, const float* __restrict__ mass,
+    const float* __restrict__ x0, const float* __restrict__ xyz, float* __restrict__ v,
+    int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx,
+    uint64_t* __restrict__ step, int kick, uint32_t* __restrict__ err)
 {
     const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_md_last(
     const int rep = tl.x;
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
     const int li = tl.y * 64 + lane;
-    double et = 0.0, ke = 0.0;
+    double et = 0.0, kin = 0.0;
     if (li < n) {
         const int a = a0 + li;
         const double m = mass[a], im = ACC_CONV / m;
@@ -93,13 +94,14 @@ __global__ __launch_bounds__(256) void k_md_last(
                 vv += hdt * from_fixed(f, INV_FX_FORCE) * im;
                 v[idx] = (float)vv;
             }
-            ke += 0.5 * m * (double)(float)vv * (double)(float)vv / ACC_CONV;
+            kin += 0.5 * m * (double)(float)vv * (double)(float)vv / ACC_CONV;
         }
     }
-    const double se = wave_sum_d(et), sk = wave_sum_d(ke);
+    const double se = wave_sum_d(et), sk = wave_sum_d(kin);
     if (lane == 0) {
         atomic_add_fx(&energy_fx[4 * rep + 3], to_fixed(se, FX_ENERGY, err));
         atomic_add_fx(&ke_fx[rep], to_fixed(sk, FX_ENERGY, err));
+        if (kick && t == 0) step[0] = step[0] + 1;
     }
 }
 
@@ -351,7 +353,8 @@ __global__ void k_exchange(gbr_grid G, uint64_t attempt, const uint64_t* __restr
     const int Gp = G.nE * G.npH * G.nT;
     const int gg = blockIdx.x * blockDim.x + threadIdx.x;
     if (gg >= Gp * G.n_inst) return;
-    const uint64_t a = step_dev ? (step_dev[0] + 1) / (uint64_t)ex_every - 1 : attempt;
+    // step_dev[0] = n + 1 once the step's force evaluation and kick are done
+    const uint64_t a = step_dev ? step_dev[0] / (uint64_t)ex_every - 1 : attempt;
     const int d = G.dim_order[a % (uint64_t)G.n_dims];
     const int parity = (int)((a / (uint64_t)G.n_dims) & 1);
     const int inst = gg / Gp, g = gg % Gp;
@@ -431,11 +434,6 @@ hipError_t launch_set_step(const gbr_ctx* c, uint64_t step0, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_step_begin(const gbr_ctx* c, hipStream_t s) {
-    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, c->step);
-    return hipGetLastError();
-}
-
 hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, hipStream_t s) {
     const double hdt = 0.5 * a.pr.dt;
     const double c1 = exp(-a.pr.gamma * a.pr.dt);
@@ -443,17 +441,22 @@ hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_md_first, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, c->n_atoms, c->step, a.seed, hdt, c1, c2, a.pr.mass,
                        a.pr.grid.T_vals, a.st.target_idx, a.st.xyz, a.st.v, a.st.force_fx,
-                       a.st.energy_fx, c->psi_fx, c->dEdR_fx, c->ke_fx);
+                       a.st.energy_fx, c->psi_fx, c->dEdR_fx, c->ke_fx, a.st.ke);
     return hipGetLastError();
 }
 
 hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s) {
     hipLaunchKernelGGL(k_md_last, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
-                       c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.mass, a.pr.x0,
-                       a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx, kick, c->err);
-    if (a.st.ke)
-        hipLaunchKernelGGL(k_ke_out, dim3((c->n_rep + 255) / 256), dim3(256), 0, s, c->n_rep,
-                           c->ke_fx, a.st.ke);
+                       c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.mass,
+                       a.pr.x0, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx,
+                       c->step, kick, c->err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ke_out(const gbr_ctx* c, double* ke, hipStream_t s) {
+    if (!ke) return hipSuccess;
+    hipLaunchKernelGGL(k_ke_out, dim3((c->n_rep + 255) / 256), dim3(256), 0, s, c->n_rep,
+                       c->ke_fx, ke);
     return hipGetLastError();
 }
 

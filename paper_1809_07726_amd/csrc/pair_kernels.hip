@@ -27,6 +27,8 @@
 // Items are visited grid-stride by a persistent grid whose block index is
 // remapped so that the blocks of one XCD (blocks are dealt round-robin to the
 // eight XCDs) walk a contiguous range of the item list, i.e. of replicas.
+#include <type_traits>
+
 #include "gbr_device.h"
 #include "gbr_internal.h"
 
@@ -86,7 +88,7 @@ __device__ __forceinline__ bool both_far(float r, float mi, float mj, float sxi,
 
 // ------------------------------------------------------------- descreening
 // Distant spheres: h = (x^3/r) G(x^2) with x = s/r, i.e. h = s^3 r^-4 G(s^2 r^-2).
-// j tile in LDS: {x, y, z, s^2}, {rt, m, sx, s^3}
+// j tile in LDS: {x, y, z, s}, {rt, m, sx, s^3}
 template <int NI>
 __global__ __launch_bounds__(256) void k_born_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
@@ -118,40 +120,46 @@ __global__ __launch_bounds__(256) void k_born_pair(
         {
             const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
             const float rt = rho[ja] - offset, s = screen[ja] * rt;
-            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s * s);
+            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s);
             lds[wv][1][lane] = make_float4(rt, fmaxf(rt, s), s * ixmax, s * s * s);
         }
         wave_lds_fence();
         float accj = 0.0f;
-        for (int k = 0; k < 64; ++k) {
-            const int m = (lane + k + 1) & 63;
-            const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
-            const int lj = g.jbase + m;
-            const bool jok = m < g.nj;
-            float cj = 0.0f;
+        // FULL: the whole I block precedes a full J tile, so no pair is masked.
+        auto kloop = [&](auto full) {
+            constexpr bool FULL = decltype(full)::value;
+            for (int k = 0; k < 64; ++k) {
+                const int m = (lane + k + 1) & 63;
+                const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
+                const int lj = g.jbase + m;
+                const bool jok = m < g.nj;
+                const float sj = p0.w, s2j = sj * sj;
+                float cj = 0.0f;
 #pragma unroll
-            for (int u = 0; u < NI; ++u) {
-                if (u < g.u_lim) {
-                    const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    r2 = (jok && li[u] < lj) ? r2 : FAR_R2;
-                    const float rinv = frsq(r2);
-                    const float rinv2 = rinv * rinv;
-                    const float rinv4 = rinv2 * rinv2;
-                    float hij = (p1.w * rinv4) * poly_G(p0.w * rinv2);
-                    float hji = (s3i[u] * rinv4) * poly_G(s2i[u] * rinv2);
-                    const float r = r2 * rinv;
-                    if (!both_far(r, mi[u], p1.y, sxi[u], p1.z)) {
-                        const float sj = p1.z * HCT_FAR_XMAX;
-                        hij = (r + sj <= rti[u]) ? 0.0f : hct_closed(r, rinv, rti[u], sj);
-                        hji = (r + si[u] <= p1.x) ? 0.0f : hct_closed(r, rinv, p1.x, si[u]);
+                for (int u = 0; u < NI; ++u) {
+                    if (FULL || u < g.u_lim) {
+                        const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+                        float r2 = dx * dx + dy * dy + dz * dz;
+                        if (!FULL) r2 = (jok && li[u] < lj) ? r2 : FAR_R2;
+                        const float rinv = frsq(r2);
+                        const float rinv2 = rinv * rinv;
+                        const float rinv4 = rinv2 * rinv2;
+                        float hij = (p1.w * rinv4) * poly_G(s2j * rinv2);
+                        float hji = (s3i[u] * rinv4) * poly_G(s2i[u] * rinv2);
+                        const float r = r2 * rinv;
+                        if (!both_far(r, mi[u], p1.y, sxi[u], p1.z)) {
+                            hij = (r + sj <= rti[u]) ? 0.0f : hct_closed(r, rinv, rti[u], sj);
+                            hji = (r + si[u] <= p1.x) ? 0.0f : hct_closed(r, rinv, p1.x, si[u]);
+                        }
+                        acc[u] += hij;
+                        cj = (u == 0) ? hji : cj + hji;
                     }
-                    acc[u] += hij;
-                    cj += hji;
                 }
+                accj = rot_add(accj, cj);
             }
-            accj = rot_add(accj, cj);
-        }
+        };
+        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{});
+        else kloop(std::false_type{});
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u)
@@ -213,62 +221,72 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         wave_lds_fence();
         float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, dRj = 0.0f, dqj = 0.0f;
         float e_c = 0.0f, e_g = 0.0f, e_lj = 0.0f;
-        for (int k = 0; k < 64; ++k) {
-            const int m = (lane + k + 1) & 63;
-            const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
-            const int lj = g.jbase + m;
-            const bool jok = m < g.nj;
-            float cx = 0.0f, cy = 0.0f, cz = 0.0f, cR = 0.0f, cq = 0.0f;
+        // FULL: the whole I block precedes a full J tile, so no pair is masked.
+        auto kloop = [&](auto full) {
+            constexpr bool FULL = decltype(full)::value;
+            for (int k = 0; k < 64; ++k) {
+                const int m = (lane + k + 1) & 63;
+                const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
+                const int lj = g.jbase + m;
+                const bool jok = m < g.nj;
+                float cx = 0.0f, cy = 0.0f, cz = 0.0f, cR = 0.0f, cq = 0.0f;
 #pragma unroll
-            for (int u = 0; u < NI; ++u) {
-                if (u < g.u_lim) {
-                    const bool valid = jok && li[u] < lj;
-                    const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    const float rinv = valid ? frsq(r2) : 0.0f;
-                    const float rinv2 = rinv * rinv;
-                    const float qq = qi[u] * p0.w;
-                    const float ec = qq * rinv;
-                    const float D2 = r2 * (Li[u] * p1.y);          // D log2(e)
-                    const float ex = __builtin_amdgcn_exp2f(-D2);   // exp(-D)
-                    const float f2 = __builtin_fmaf(Ri[u] * p1.x, ex, r2);
-                    const float finv = valid ? frsq(f2) : 0.0f;
-                    const float eg = qq * finv;
-                    const float t = eg * finv * finv;               // qq / f^3
-                    const float sgr = (hsi[u] + p1.z) * rinv;
-                    const float s2 = sgr * sgr;
-                    const float s6 = s2 * s2 * s2;
-                    const float A = (sei[u] * p1.w) * s6;           // 4 eps_ij s^6
-                    const float B = A * s6;                         // 4 eps_ij s^12
-                    const float elj = B - A;
-                    const float uu = __builtin_fmaf(6.0f, B + elj, ec);
-                    const float w = __builtin_fmaf(ex, wq, taup);   // tau' (1 - exp(-D)/4)
-                    const float fs = __builtin_fmaf(-uu, rinv2, t * w);
-                    const float gR = t * ex * __builtin_fmaf(D2, hl, 0.5f);
-                    e_c += ec;
-                    e_g += eg;
-                    e_lj += elj;
-                    fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
-                    fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
-                    fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
-                    cx = __builtin_fmaf(-fs, dx, cx);
-                    cy = __builtin_fmaf(-fs, dy, cy);
-                    cz = __builtin_fmaf(-fs, dz, cz);
-                    dRi[u] = __builtin_fmaf(gR, p1.x, dRi[u]);
-                    cR = __builtin_fmaf(gR, Ri[u], cR);
-                    if (GQ) {
-                        const float wqq = __builtin_fmaf(-taup, finv, rinv);
-                        dqi[u] = __builtin_fmaf(wqq, p0.w, dqi[u]);
-                        cq = __builtin_fmaf(wqq, qi[u], cq);
+                for (int u = 0; u < NI; ++u) {
+                    if (FULL || u < g.u_lim) {
+                        const bool valid = FULL || (jok && li[u] < lj);
+                        const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        const float rinv = valid ? frsq(r2) : 0.0f;
+                        const float rinv2 = rinv * rinv;
+                        const float qq = qi[u] * p0.w;
+                        const float ec = qq * rinv;
+                        const float D2 = r2 * (Li[u] * p1.y);          // D log2(e)
+                        const float ex = __builtin_amdgcn_exp2f(-D2);   // exp(-D)
+                        const float f2 = __builtin_fmaf(Ri[u] * p1.x, ex, r2);
+                        const float finv = valid ? frsq(f2) : 0.0f;
+                        const float eg = qq * finv;
+                        const float t = eg * finv * finv;               // qq / f^3
+                        const float sgr = (hsi[u] + p1.z) * rinv;
+                        const float s2 = sgr * sgr;
+                        const float s6 = s2 * s2 * s2;
+                        const float A = (sei[u] * p1.w) * s6;           // 4 eps_ij s^6
+                        const float B = A * s6;                         // 4 eps_ij s^12
+                        const float elj = B - A;
+                        const float uu = __builtin_fmaf(6.0f, B + elj, ec);
+                        const float w = __builtin_fmaf(ex, wq, taup);   // tau' (1 - exp(-D)/4)
+                        const float fs = __builtin_fmaf(-uu, rinv2, t * w);
+                        const float gR = t * ex * __builtin_fmaf(D2, hl, 0.5f);
+                        e_c += ec;
+                        e_g += eg;
+                        e_lj += elj;
+                        fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
+                        fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
+                        fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
+                        dRi[u] = __builtin_fmaf(gR, p1.x, dRi[u]);
+                        if (u == 0) {
+                            cx = -fs * dx; cy = -fs * dy; cz = -fs * dz; cR = gR * Ri[u];
+                        } else {
+                            cx = __builtin_fmaf(-fs, dx, cx);
+                            cy = __builtin_fmaf(-fs, dy, cy);
+                            cz = __builtin_fmaf(-fs, dz, cz);
+                            cR = __builtin_fmaf(gR, Ri[u], cR);
+                        }
+                        if (GQ) {
+                            const float wqq = __builtin_fmaf(-taup, finv, rinv);
+                            dqi[u] = __builtin_fmaf(wqq, p0.w, dqi[u]);
+                            cq = (u == 0) ? wqq * qi[u] : __builtin_fmaf(wqq, qi[u], cq);
+                        }
                     }
                 }
+                fxj = rot_add(fxj, cx);
+                fyj = rot_add(fyj, cy);
+                fzj = rot_add(fzj, cz);
+                dRj = rot_add(dRj, cR);
+                if (GQ) dqj = rot_add(dqj, cq);
             }
-            fxj = rot_add(fxj, cx);
-            fyj = rot_add(fyj, cy);
-            fzj = rot_add(fzj, cz);
-            dRj = rot_add(dRj, cR);
-            if (GQ) dqj = rot_add(dqj, cq);
-        }
+        };
+        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{});
+        else kloop(std::false_type{});
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
@@ -347,53 +365,62 @@ __global__ __launch_bounds__(256) void k_chain_pair(
         }
         wave_lds_fence();
         float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, drj = 0.0f;
-        for (int k = 0; k < 64; ++k) {
-            const int m = (lane + k + 1) & 63;
-            const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m], p2 = lds[wv][2][m];
-            const int lj = g.jbase + m;
-            const bool jok = m < g.nj;
-            float cx = 0.0f, cy = 0.0f, cz = 0.0f, cr = 0.0f;
+        // FULL: the whole I block precedes a full J tile, so no pair is masked.
+        auto kloop = [&](auto full) {
+            constexpr bool FULL = decltype(full)::value;
+            for (int k = 0; k < 64; ++k) {
+                const int m = (lane + k + 1) & 63;
+                const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m], p2 = lds[wv][2][m];
+                const int lj = g.jbase + m;
+                const bool jok = m < g.nj;
+                float cx = 0.0f, cy = 0.0f, cz = 0.0f, cr = 0.0f;
 #pragma unroll
-            for (int u = 0; u < NI; ++u) {
-                if (u < g.u_lim) {
-                    const bool valid = jok && li[u] < lj;
-                    const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    r2 = valid ? r2 : FAR_R2;
-                    const float rinv = frsq(r2);
-                    const float r = r2 * rinv;
-                    const float rinv2 = rinv * rinv;
-                    float fs;
-                    if (!RHO) {
-                        const float Qij = poly_Q(p2.x * rinv2), Qji = poly_Q(s2i[u] * rinv2);
-                        const float G = __builtin_fmaf(p0.w * s3i[u], Qji, ci[u] * (p2.y * Qij));
-                        fs = -G * (rinv2 * rinv2 * rinv2);
-                        if (!both_far(r, mi[u], p1.z, sxi[u], p1.w)) {
-                            const float dij = (r + p1.y <= rti[u]) ? 0.0f : hct_dr_closed(r, rinv, rti[u], p1.y);
-                            const float dji = (r + si[u] <= p1.x) ? 0.0f : hct_dr_closed(r, rinv, p1.x, si[u]);
-                            fs = (ci[u] * dij + p0.w * dji) * rinv;
+                for (int u = 0; u < NI; ++u) {
+                    if (FULL || u < g.u_lim) {
+                        const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+                        float r2 = dx * dx + dy * dy + dz * dz;
+                        if (!FULL) r2 = (jok && li[u] < lj) ? r2 : FAR_R2;
+                        const float rinv = frsq(r2);
+                        const float r = r2 * rinv;
+                        const float rinv2 = rinv * rinv;
+                        float fs;
+                        if (!RHO) {
+                            const float Qij = poly_Q(p2.x * rinv2), Qji = poly_Q(s2i[u] * rinv2);
+                            const float G = __builtin_fmaf(p0.w * s3i[u], Qji, ci[u] * (p2.y * Qij));
+                            fs = -G * (rinv2 * rinv2 * rinv2);
+                            if (!both_far(r, mi[u], p1.z, sxi[u], p1.w)) {
+                                const float dij = (r + p1.y <= rti[u]) ? 0.0f : hct_dr_closed(r, rinv, rti[u], p1.y);
+                                const float dji = (r + si[u] <= p1.x) ? 0.0f : hct_dr_closed(r, rinv, p1.x, si[u]);
+                                fs = (ci[u] * dij + p0.w * dji) * rinv;
+                            }
+                        } else {
+                            float dr_ij, drt_ij, ds_ij, dr_ji, drt_ji, ds_ji;
+                            hct_grad3(r, rinv, rti[u], p1.y, dr_ij, drt_ij, ds_ij);
+                            hct_grad3(r, rinv, p1.x, si[u], dr_ji, drt_ji, ds_ji);
+                            fs = (ci[u] * dr_ij + p0.w * dr_ji) * rinv;
+                            dri[u] += ci[u] * drt_ij + Si[u] * p0.w * ds_ji;
+                            cr += p0.w * drt_ji + p2.z * ci[u] * ds_ij;
                         }
-                    } else {
-                        float dr_ij, drt_ij, ds_ij, dr_ji, drt_ji, ds_ji;
-                        hct_grad3(r, rinv, rti[u], p1.y, dr_ij, drt_ij, ds_ij);
-                        hct_grad3(r, rinv, p1.x, si[u], dr_ji, drt_ji, ds_ji);
-                        fs = (ci[u] * dr_ij + p0.w * dr_ji) * rinv;
-                        dri[u] += ci[u] * drt_ij + Si[u] * p0.w * ds_ji;
-                        cr += p0.w * drt_ji + p2.z * ci[u] * ds_ij;
+                        fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
+                        fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
+                        fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
+                        if (u == 0) {
+                            cx = -fs * dx; cy = -fs * dy; cz = -fs * dz;
+                        } else {
+                            cx = __builtin_fmaf(-fs, dx, cx);
+                            cy = __builtin_fmaf(-fs, dy, cy);
+                            cz = __builtin_fmaf(-fs, dz, cz);
+                        }
                     }
-                    fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
-                    fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
-                    fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
-                    cx = __builtin_fmaf(-fs, dx, cx);
-                    cy = __builtin_fmaf(-fs, dy, cy);
-                    cz = __builtin_fmaf(-fs, dz, cz);
                 }
+                fxj = rot_add(fxj, cx);
+                fyj = rot_add(fyj, cy);
+                fzj = rot_add(fzj, cz);
+                if (RHO) drj = rot_add(drj, cr);
             }
-            fxj = rot_add(fxj, cx);
-            fyj = rot_add(fyj, cy);
-            fzj = rot_add(fzj, cz);
-            if (RHO) drj = rot_add(drj, cr);
-        }
+        };
+        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{});
+        else kloop(std::false_type{});
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
