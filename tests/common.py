@@ -29,3 +29,70 @@ def with_oracle_gref(batch, gb=None):
     b = dict(batch)
     b["G_ref"] = oracle_reference_energies(batch, gb)
     return b
+
+
+# ------------------------------------------------ coupled-site model system
+def coupled_sites_system(seed=41, pH_vals=(6.5,), E_vals=(-0.2,), T_vals=(300.0,), n_inst=1):
+    """The atoms of one pH site and one redox site (taken from a 64-atom
+    lattice system) as a frozen system: dt = 0, attempts every step.  With G_ref
+    from the isolated sites (oracle), replicas on an E x pH grid."""
+    src = synth.make_config(0, n_atoms=64, seed=seed)
+    ms = src["max_states"]
+    idx = np.concatenate([src["site_atoms"][src["site_off"][s]:src["site_off"][s + 1]] for s in (0, 1)])
+    sysd = {k: src[k][idx] for k in ("xyz", "x0", "q", "rho", "screen", "sigma", "eps", "mass")}
+    sysd["sites"] = []
+    pos = 0
+    for s in (0, 1):
+        a, c = src["site_off"][s], src["site_off"][s + 1]
+        t = int(src["site_type"][s])
+        sysd["sites"].append({"type": t, "atoms": np.arange(pos, pos + (c - a)),
+                              "q_states": src["state_q"].reshape(-1, ms)[a:c],
+                              "nH": [0, 1] if t == 0 else [0, 0], "ne": [0, 0] if t == 0 else [0, 1],
+                              "ref": src["ref_value"][s]})
+        pos += c - a
+    G = len(E_vals) * len(pH_vals) * len(T_vals)
+    dims = (synth.DIM_E, synth.DIM_PH) + ((synth.DIM_T,) if len(T_vals) > 1 else ())
+    b = synth.assemble([sysd] * n_inst, G, E_vals, pH_vals, tuple(T_vals), dims,
+                       dt=0.0, mc_every=1, ex_every=2)
+    return with_oracle_gref(b)
+
+
+def four_state_energies(b, gb=None):
+    """eps[sH, se] = E_elec(state charges) - G_ref,H(sH) - G_ref,e(se) for the
+    first replica of a coupled-site batch (site 0 = pH, site 1 = redox)."""
+    n0 = b["atom_off"][1]
+    x, q0 = b["xyz"][:n0].astype(np.float64), b["q"][:n0].astype(np.float64)
+    _, R, _ = oracle.born(x, b["rho"][:n0], b["screen"][:n0], gb)
+    ms = b["max_states"]
+    eps = np.zeros((2, 2))
+    for sH in (0, 1):
+        for se in (0, 1):
+            q = q0.copy()
+            for s, st in ((0, sH), (1, se)):
+                a, c = b["site_off"][s], b["site_off"][s + 1]
+                q[b["site_atoms"][a:c]] = b["state_q"].reshape(-1, ms)[a:c, st]
+            eps[sH, se] = (oracle.elec_energy(x, q, R, gb) - b["G_ref"][0 * ms + sH]
+                           - b["G_ref"][1 * ms + se])
+    return eps
+
+
+def four_state_probs(eps, pH, E, T, pKa, E0):
+    c = oracle.constants()
+    kT = c["kB"] * T
+    w = np.zeros((2, 2))
+    for sH in (0, 1):
+        for se in (0, 1):
+            g = eps[sH, se] + kT * c["ln10"] * (pH - pKa) * sH + c["F"] * (E - E0) * se
+            w[sH, se] = -g / kT
+    w = np.exp(w - w.max())
+    return w / w.sum()
+
+
+def four_state_constants(eps, T, pKa, E0):
+    """pKa_oxi, pKa_red, E0_deprot, E0_prot of the frozen coupled model."""
+    c = oracle.constants()
+    kT = c["kB"] * T
+    return {"pKa_oxi": pKa - (eps[1, 0] - eps[0, 0]) / (kT * c["ln10"]),
+            "pKa_red": pKa - (eps[1, 1] - eps[0, 1]) / (kT * c["ln10"]),
+            "E0_deprot": E0 - (eps[0, 1] - eps[0, 0]) / c["F"],
+            "E0_prot": E0 - (eps[1, 1] - eps[1, 0]) / c["F"]}
