@@ -108,6 +108,10 @@ def cpu_baseline(b, n_rep_sample, budget_s=15.0):
                       f"Born-radii + energy + analytic-gradient evaluation each ({dt:.1f} s)"}
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,12 +133,15 @@ def main():
     n_pairs = ctx.n_pairs
     stream = torch.cuda.current_stream()
 
+    _progress(f"{w.name}: {b['n_rep']} replicas, {n_pairs} pairs per step; autotuning")
     tuned = autotune(ctx, dev.t)
+    _progress(f"tuned {tuned}; warmup")
     md.run(0, init_forces=True)
     md.run(args.warmup if not args.profile_only else 3, graph=args.graph)
     torch.cuda.synchronize()
     ctx.check()
     K = args.steps if not args.profile_only else 5
+    _progress(f"timing {K} steps")
     ctx.set_timing(not args.graph, ("born_pair", "energy_pair", "chain_pair"))
     ctx.get_timing()                       # reset
     torch.cuda.synchronize()
@@ -178,6 +185,7 @@ def main():
     pair_ms = sum(v["avg_ms"] for v in per_kernel.values())
     all_pairs_tflops = FLOP_PAIR * n_pairs / (pair_ms * 1e-3) / 1e12 if pair_ms else None
 
+    _progress(f"{ms_step:.4f} ms/step; batched vs per-replica evaluation")
     # batched vs per-replica plain E+F evaluation (same kernels, one launch sequence per replica)
     evals = {}
     t = dev.t
@@ -226,6 +234,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        _progress("oracle CPU baseline")
         cpu = cpu_baseline(b, args.cpu_sample_replicas)
 
     out = {

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "gbr_internal.h"
+#include "pair_list.h"
 
 using namespace gbr;
 
@@ -104,18 +105,6 @@ int check_grid(const gbr_ctx* c, const gbr_grid& g) {
     for (int k = 0; k < g.n_dims; ++k)
         if (g.dim_order[k] < 0 || g.dim_order[k] > 2) return fail(GBR_E_INVAL, "bad dim_order");
     return GBR_OK;
-}
-
-void build_pair_list(const std::vector<int32_t>& off, int ni, std::vector<int2>& out) {
-    out.clear();
-    const int n_rep = (int)off.size() - 1;
-    for (int r = 0; r < n_rep; ++r) {
-        const int n = off[r + 1] - off[r];
-        const int T = (n + 63) / 64;
-        const int B = (n + 64 * ni - 1) / (64 * ni);
-        for (int ib = 0; ib < B; ++ib)
-            for (int j = ib * ni; j < T; ++j) out.push_back(make_int2(r, (ib << 16) | j));
-    }
 }
 
 int upload(void* dst, const void* src, size_t bytes) {
@@ -231,7 +220,7 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     if (!out) return fail(GBR_E_INVAL, "out is null");
     *out = nullptr;
     if (!params) return fail(GBR_E_INVAL, "params is null");
-    if (n_rep < 1) return fail(GBR_E_INVAL, "n_rep must be >= 1");
+    if (n_rep < 1 || n_rep >= gbr::MAX_REPLICAS) return fail(GBR_E_INVAL, "n_rep out of range");
     if (!atom_off_host) return fail(GBR_E_INVAL, "atom_off_host is null");
     if (atom_off_host[0] != 0) return fail(GBR_E_INVAL, "atom_off[0] must be 0");
     int64_t pairs = 0;
@@ -239,7 +228,7 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     for (int r = 0; r < n_rep; ++r) {
         const int n = atom_off_host[r + 1] - atom_off_host[r];
         if (n < 1) return fail(GBR_E_INVAL, "replica %d has %d atoms", r, n);
-        if (n > 64 * 65535) return fail(GBR_E_INVAL, "replica %d too large", r);
+        if (n > 64 * gbr::MAX_TILES) return fail(GBR_E_INVAL, "replica %d too large", r);
         max_n = std::max(max_n, n);
         pairs += (int64_t)n * (n - 1) / 2;
     }
@@ -280,9 +269,10 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     if ((rc = dev_alloc(&c->tiles, tl.size()))) return done(rc);
     if ((rc = upload(c->tiles, tl.data(), sizeof(int2) * tl.size()))) return done(rc);
     const int nis[4] = {1, 2, 4, 8};
-    std::vector<int2> items;
+    std::vector<gbr::PairItem> items;
+    static_assert(sizeof(gbr::PairItem) == sizeof(int2), "item layout");
     for (int k = 0; k < 4; ++k) {
-        build_pair_list(c->h_atom_off, nis[k], items);
+        gbr::build_pair_items(c->h_atom_off.data(), n_rep, nis[k], items);
         if (items.size() > 0x7FFFFFFF) return done(fail(GBR_E_INVAL, "work list too long"));
         c->lists[k].ni = nis[k];
         c->lists[k].n_items = (int32_t)items.size();

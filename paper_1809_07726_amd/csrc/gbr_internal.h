@@ -12,10 +12,10 @@
 
 namespace gbr {
 
-// Pair work item: replica, I-block (NI*64 atoms) and J-tile (64 atoms).
+// Pair work list of one register blocking (items as in pair_list.h).
 struct PairList {
     int ni = 0;                // i atoms per lane the list was built for
-    int2* items = nullptr;     // {rep, (IB << 16) | J}
+    int2* items = nullptr;     // {rep | type << 30, (A << 16) | B}
     int32_t n_items = 0;
 };
 

@@ -1,28 +1,27 @@
 // pair_kernels.hip -- the three O(N^2) pair passes of a GB evaluation.
 //
-// Work decomposition (same for the three passes).  Replica r with n atoms is
-// cut into 64-atom J tiles and (64 * NI)-atom I blocks.  A work item
-// (r, IB, J) is the set of pairs (i, j) with i in block IB, j in tile J and
-// i < j (local indices), so every unordered pair of every replica belongs to
-// exactly one item; items exist for J >= IB * NI.  One wavefront processes one
-// item.  Lane l holds the NI atoms i = IB*64*NI + u*64 + l (u < NI) in
-// registers; the J tile is copied to a per-wavefront LDS slice.
+// Work decomposition (same for the three passes; the item list is described
+// in pair_list.h).  One wavefront processes one item.  In a block item lane l
+// holds the NI atoms i = IB*64*NI + u*64 + l (u < NI) in registers; in a
+// square or triangle item it holds one atom of tile A.  The j tile is copied
+// to a per-wavefront LDS slice.
 //
-// Rotating j accumulators: in step k (0..63) lane l pairs its i atoms with
+// Rotating j accumulators: in step k lane l pairs its i atoms with
 // j = (l + k + 1) mod 64, read from LDS, and adds its contribution into a
 // per-lane accumulator that is first rotated by one lane (DPP wave_rol:1,
 // folded into the add).  The accumulator that lane l adds into in step k
-// therefore always belongs to the j it is working on, and after 64 steps every
-// accumulator is back on the lane of its own j.  This replaces a 64-lane
-// reduction per j with one DPP add per component per step.
+// therefore always belongs to the j it is working on; after K steps lane l
+// holds the accumulator of j = (l + K) mod 64 (K = 64 for blocks and squares,
+// 32 for triangles).  This replaces a 64-lane reduction per j with one DPP add
+// per component per step.
 //
 // Contributions to i accumulate per lane in FP32.  At the end of the item
 // every per-atom partial is rounded to 64-bit fixed point and added with an
 // integer atomic, so the result does not depend on the order in which items
-// run.  Invalid pairs (i >= j, j past the end of the replica, I lanes past the
-// end) are removed by zeroing 1/r (or sending r to 1e15 A), which makes every
-// term of the pair exactly zero; I sub-blocks of 64 atoms with no valid pair in
-// an item are skipped with a uniform branch.
+// run.  Invalid pairs (j past the end of the replica, i lanes past the end of
+// a ragged triangle, the duplicated half of a triangle's last step) are
+// removed by zeroing 1/r (or sending r to 1e15 A), which makes every term of
+// the pair exactly zero; items on full tiles run an unmasked loop.
 //
 // Items are visited grid-stride by a persistent grid whose block index is
 // remapped so that the blocks of one XCD (blocks are dealt round-robin to the
@@ -31,6 +30,7 @@
 
 #include "gbr_device.h"
 #include "gbr_internal.h"
+#include "pair_list.h"
 
 using namespace gbr;
 
@@ -59,23 +59,55 @@ __device__ __forceinline__ void wave_lds_fence() {
 }
 
 struct ItemGeom {
-    int rep, a0, n, ibase, jbase, nj, u_lim;
+    int rep, a0, n, ibase, jbase, nj;
+    int u_lim;      // i sub-blocks with a valid pair
+    bool tri;       // triangle item (NI = 1 only)
+    int ksteps;     // steps of the item
 };
 
 template <int NI>
 __device__ __forceinline__ ItemGeom item_geom(const int2 wi, const int32_t* __restrict__ atom_off) {
     ItemGeom g;
-    g.rep = wi.x;
-    const int IB = wi.y >> 16, J = wi.y & 0xFFFF;
+    g.rep = wi.x & 0x3FFFFFFF;
+    const int A = wi.y >> 16, B = wi.y & 0xFFFF;
     g.a0 = atom_off[g.rep];
     g.n = atom_off[g.rep + 1] - g.a0;
-    g.ibase = IB * 64 * NI;
-    g.jbase = J * 64;
+    g.ibase = A * 64 * NI;
+    g.jbase = B * 64;
     g.nj = min(64, g.n - g.jbase);
+    g.tri = NI == 1 && ((unsigned)wi.x >> 30) == ITEM_TRIANGLE;
+    g.ksteps = g.tri ? 32 : 64;
     // I sub-blocks u with a valid pair: ibase + 64u < jbase + nj (and < n)
     const int span = g.jbase + g.nj - g.ibase;
     g.u_lim = min(NI, (span + 63) >> 6);
     return g;
+}
+
+// Validity of the pair of sub-block u in the masked loop (step k, j tile slot
+// m): j inside the replica and, in a block item on the diagonal, i < j; in a
+// triangle both atoms inside the replica and only lanes 0..31 on step 31.
+template <int NI>
+__device__ __forceinline__ bool pair_ok(const ItemGeom& g, int lane, int k, int m, int li) {
+    const bool jok = m < g.nj;
+    if (NI == 1 && g.tri) return jok & (lane < g.nj) & ((k < 31) | (lane < 32));
+    return jok & (li < g.jbase + m);
+}
+
+// Runs an item through the step loop kloop(full, k0, k1): the unmasked loop
+// for a block item that lies entirely before a full j tile, and for the first
+// 31 steps of a triangle on a full tile; the masked loop for the rest.  Each
+// variant is called from one place so that it is inlined.
+template <int NI, typename K>
+__device__ __forceinline__ void run_item(const ItemGeom& g, K& kloop) {
+    if constexpr (NI == 1) {
+        int f1 = 0;
+        if (g.nj == 64) f1 = g.tri ? 31 : 64;
+        if (f1 > 0) kloop(std::true_type{}, 0, f1);
+        if (f1 < g.ksteps) kloop(std::false_type{}, f1, g.ksteps);
+    } else {
+        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{}, 0, 64);
+        else kloop(std::false_type{}, 0, 64);
+    }
 }
 
 // Far-sphere test for both descreening directions of a pair: with
@@ -125,14 +157,11 @@ __global__ __launch_bounds__(256) void k_born_pair(
         }
         wave_lds_fence();
         float accj = 0.0f;
-        // FULL: the whole I block precedes a full J tile, so no pair is masked.
-        auto kloop = [&](auto full) {
+        auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
-            for (int k = 0; k < 64; ++k) {
+            for (int k = k0; k < k1; ++k) {
                 const int m = (lane + k + 1) & 63;
                 const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
-                const int lj = g.jbase + m;
-                const bool jok = m < g.nj;
                 const float sj = p0.w, s2j = sj * sj;
                 float cj = 0.0f;
 #pragma unroll
@@ -140,7 +169,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
                     if (FULL || u < g.u_lim) {
                         const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
                         float r2 = dx * dx + dy * dy + dz * dz;
-                        if (!FULL) r2 = (jok && li[u] < lj) ? r2 : FAR_R2;
+                        if (!FULL) r2 = pair_ok<NI>(g, lane, k, m, li[u]) ? r2 : FAR_R2;
                         const float rinv = frsq(r2);
                         const float rinv2 = rinv * rinv;
                         const float rinv4 = rinv2 * rinv2;
@@ -158,14 +187,14 @@ __global__ __launch_bounds__(256) void k_born_pair(
                 accj = rot_add(accj, cj);
             }
         };
-        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{});
-        else kloop(std::false_type{});
+        run_item<NI>(g, kloop);
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u)
-            if (li[u] < g.n) atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed(acc[u], FX_FORCE, err));
-        if (g.jbase + lane < g.n)
-            atomic_add_fx(&psi_fx[g.a0 + g.jbase + lane], to_fixed(accj, FX_FORCE, err));
+            if (li[u] < g.n)
+                atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed(acc[u], FX_FORCE, err));
+        const int jl = g.jbase + ((lane + g.ksteps) & 63);
+        if (jl < g.n) atomic_add_fx(&psi_fx[g.a0 + jl], to_fixed(accj, FX_FORCE, err));
     }
 }
 
@@ -221,19 +250,16 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         wave_lds_fence();
         float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, dRj = 0.0f, dqj = 0.0f;
         float e_c = 0.0f, e_g = 0.0f, e_lj = 0.0f;
-        // FULL: the whole I block precedes a full J tile, so no pair is masked.
-        auto kloop = [&](auto full) {
+        auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
-            for (int k = 0; k < 64; ++k) {
+            for (int k = k0; k < k1; ++k) {
                 const int m = (lane + k + 1) & 63;
                 const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
-                const int lj = g.jbase + m;
-                const bool jok = m < g.nj;
                 float cx = 0.0f, cy = 0.0f, cz = 0.0f, cR = 0.0f, cq = 0.0f;
 #pragma unroll
                 for (int u = 0; u < NI; ++u) {
                     if (FULL || u < g.u_lim) {
-                        const bool valid = FULL || (jok && li[u] < lj);
+                        const bool valid = FULL || pair_ok<NI>(g, lane, k, m, li[u]);
                         const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         const float rinv = valid ? frsq(r2) : 0.0f;
@@ -285,8 +311,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
                 if (GQ) dqj = rot_add(dqj, cq);
             }
         };
-        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{});
-        else kloop(std::false_type{});
+        run_item<NI>(g, kloop);
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
@@ -299,8 +324,9 @@ __global__ __launch_bounds__(256) void k_energy_pair(
                 if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)dqi[u] * sq_ke_in, FX_FORCE, err));
             }
         }
-        if (g.jbase + lane < g.n) {
-            const int a = g.a0 + g.jbase + lane;
+        const int jl = g.jbase + ((lane + g.ksteps) & 63);
+        if (jl < g.n) {
+            const int a = g.a0 + jl;
             atomic_add_fx(&force_fx[a], to_fixed(fxj, FX_FORCE, err));
             atomic_add_fx(&force_fx[ntot + a], to_fixed(fyj, FX_FORCE, err));
             atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzj, FX_FORCE, err));
@@ -365,21 +391,18 @@ __global__ __launch_bounds__(256) void k_chain_pair(
         }
         wave_lds_fence();
         float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, drj = 0.0f;
-        // FULL: the whole I block precedes a full J tile, so no pair is masked.
-        auto kloop = [&](auto full) {
+        auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
-            for (int k = 0; k < 64; ++k) {
+            for (int k = k0; k < k1; ++k) {
                 const int m = (lane + k + 1) & 63;
                 const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m], p2 = lds[wv][2][m];
-                const int lj = g.jbase + m;
-                const bool jok = m < g.nj;
                 float cx = 0.0f, cy = 0.0f, cz = 0.0f, cr = 0.0f;
 #pragma unroll
                 for (int u = 0; u < NI; ++u) {
                     if (FULL || u < g.u_lim) {
                         const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
                         float r2 = dx * dx + dy * dy + dz * dz;
-                        if (!FULL) r2 = (jok && li[u] < lj) ? r2 : FAR_R2;
+                        if (!FULL) r2 = pair_ok<NI>(g, lane, k, m, li[u]) ? r2 : FAR_R2;
                         const float rinv = frsq(r2);
                         const float r = r2 * rinv;
                         const float rinv2 = rinv * rinv;
@@ -419,8 +442,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
                 if (RHO) drj = rot_add(drj, cr);
             }
         };
-        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{});
-        else kloop(std::false_type{});
+        run_item<NI>(g, kloop);
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
@@ -432,8 +454,9 @@ __global__ __launch_bounds__(256) void k_chain_pair(
                 if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(dri[u], FX_FORCE, err));
             }
         }
-        if (g.jbase + lane < g.n) {
-            const int a = g.a0 + g.jbase + lane;
+        const int jl = g.jbase + ((lane + g.ksteps) & 63);
+        if (jl < g.n) {
+            const int a = g.a0 + jl;
             atomic_add_fx(&force_fx[a], to_fixed(fxj, FX_FORCE, err));
             atomic_add_fx(&force_fx[ntot + a], to_fixed(fyj, FX_FORCE, err));
             atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzj, FX_FORCE, err));

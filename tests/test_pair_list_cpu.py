@@ -1,0 +1,104 @@
+"""The pair passes' work list (csrc/pair_list.h) built by the library's own
+host code, compiled here with g++: with the kernels' masking rules (i < j in
+block items, the half last step of a triangle), every unordered pair of every
+replica is met exactly once, for every register blocking and for ragged
+replica sizes."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1809_07726_amd", "csrc")
+
+HARNESS = r"""
+#include <cstdio>
+#include <cstdlib>
+#include "pair_list.h"
+int main(int argc, char** argv) {
+    const int ni = std::atoi(argv[1]);
+    std::vector<int32_t> off{0};
+    for (int k = 2; k < argc; ++k) off.push_back(off.back() + std::atoi(argv[k]));
+    std::vector<gbr::PairItem> items;
+    gbr::build_pair_items(off.data(), (int32_t)off.size() - 1, ni, items);
+    for (const auto& it : items)
+        std::printf("%d %d %d %d\n", it.x & 0x3FFFFFFF, (int)((unsigned)it.x >> 30), it.y >> 16, it.y & 0xFFFF);
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("pairlist")
+    src, exe = d / "h.cpp", d / "h"
+    src.write_text(HARNESS)
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)])
+    return str(exe)
+
+
+def _items(exe, ni, sizes):
+    out = subprocess.check_output([exe, str(ni)] + [str(s) for s in sizes], text=True)
+    return np.array([list(map(int, l.split())) for l in out.splitlines()], dtype=np.int64).reshape(-1, 4)
+
+
+def _pairs_of_item(n, ni, typ, A, B):
+    """Pairs (i, j) the kernels evaluate for one item, following their masks."""
+    lane = np.arange(64)
+    nj = min(64, n - 64 * B)
+    if typ == 0:                     # block: i in block A (inside the replica) x tile B, i < j
+        i = 64 * ni * A + np.arange(64 * ni)
+        i = i[i < n]
+        j = 64 * B + np.arange(nj)
+        P = np.stack(np.meshgrid(i, j, indexing="ij"), -1).reshape(-1, 2)
+        return P[P[:, 0] < P[:, 1]]
+    assert typ == 2 and A == B and ni == 1      # triangle: 32 rotation steps
+    out = []
+    for k in range(32):
+        m = (lane + k + 1) & 63
+        ok = (m < nj) & (lane < nj) & ((k < 31) | (lane < 32))
+        out.append(np.stack([64 * A + lane[ok], 64 * A + m[ok]], -1))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("ni", [1, 2, 4, 8])
+def test_every_pair_exactly_once(harness, ni):
+    sizes = [1, 2, 63, 64, 65, 127, 128, 129, 200, 511, 640, 1000]
+    items = _items(harness, ni, sizes)
+    assert np.all(np.diff(items[:, 0]) >= 0), "items grouped by replica"
+    for r, n in enumerate(sizes):
+        its = items[items[:, 0] == r]
+        P = np.concatenate([_pairs_of_item(n, ni, *it[1:]) for it in its]) if len(its) else np.zeros((0, 2), int)
+        assert np.all(P[:, 0] != P[:, 1]), (n, ni)
+        assert P.min(initial=0) >= 0 and P.max(initial=0) < n
+        a, b = np.minimum(P[:, 0], P[:, 1]), np.maximum(P[:, 0], P[:, 1])
+        key = a * n + b
+        assert key.size == n * (n - 1) // 2, (n, ni, key.size)
+        assert np.unique(key).size == key.size, (n, ni)
+
+
+def test_item_counts_per_replica(harness):
+    """NI = 1: one triangle per tile and one block item per later tile;
+    NI > 1: one block item per tile from the block's first tile on."""
+    items = _items(harness, 1, [1024])
+    assert (items[:, 1] == 2).sum() == 16 and (items[:, 1] == 0).sum() == 16 * 15 // 2
+    items = _items(harness, 2, [1024])
+    assert (items[:, 1] == 0).all() and len(items) == sum(16 - 2 * ib for ib in range(8))
+
+
+@pytest.mark.parametrize("K", [32, 64])
+def test_rotating_accumulator_lands_on_lane_plus_k(K):
+    """acc <- acc[lane + 1] + c with c the contribution of lane l to
+    j = (l + k + 1) mod 64: after K steps lane l holds the sum for
+    j = (l + K) mod 64, which is where the kernels flush it."""
+    rng = np.random.default_rng(K)
+    lane = np.arange(64)
+    contrib = np.zeros(64)
+    acc = np.zeros(64)
+    for k in range(K):
+        c = rng.normal(size=64)
+        j = (lane + k + 1) & 63
+        np.add.at(contrib, j, c)
+        acc = np.roll(acc, -1) + c
+    assert np.allclose(acc, contrib[(lane + K) & 63], rtol=0, atol=1e-12)
