@@ -82,18 +82,21 @@ def traffic_from_profile(kernel, launches_bytes_alg):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(b, n_rep_sample, budget_s=15.0):
+def cpu_baseline(b, n_rep_sample, min_s=10.0, budget_s=20.0):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
-    full E+F gradient evaluations of successive replicas until n_rep_sample
-    replicas (0: no limit) or about budget_s seconds of CPU work."""
+    full E+F gradient evaluations of successive replicas (cycling through the
+    batch) until at least min_s seconds of CPU work, stopping at budget_s or
+    after n_rep_sample evaluations (0: no count limit)."""
     import oracle
     off = b["atom_off"]
     t0 = time.perf_counter()
     pairs = 0
     done = 0
-    for r in range(b["n_rep"]):
-        if (n_rep_sample and done >= n_rep_sample) or time.perf_counter() - t0 > budget_s:
+    while True:
+        el = time.perf_counter() - t0
+        if el > budget_s or (n_rep_sample and done >= n_rep_sample) or (el >= min_s and done >= 1):
             break
+        r = done % b["n_rep"]
         done += 1
         a, c = off[r], off[r + 1]
         oracle.gradient(b["xyz"][a:c], b["q"][a:c], b["rho"][a:c], b["screen"][a:c],
@@ -104,8 +107,9 @@ def cpu_baseline(b, n_rep_sample, budget_s=15.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
     return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} of {b['n_rep']} replicas x {off[1] - off[0]} atoms: one FP64 "
-                      f"Born-radii + energy + analytic-gradient evaluation each ({dt:.1f} s)"}
+            "sample": f"{done} replica evaluations ({done / b['n_rep']:.1f} passes over the "
+                      f"{b['n_rep']} replicas x {off[1] - off[0]} atoms): one FP64 Born-radii + energy + "
+                      f"analytic-gradient evaluation each ({dt:.1f} s)"}
 
 
 def _progress(msg):
@@ -141,8 +145,13 @@ def main():
     torch.cuda.synchronize()
     ctx.check()
     K = args.steps if not args.profile_only else 5
-    _progress(f"timing {K} steps")
-    ctx.set_timing(not args.graph, ("born_pair", "energy_pair", "chain_pair"))
+    # Only the dominant pair pass (slowest in the autotuner's own timing) is
+    # bracketed by HIP events inside the timed region: every event pair costs
+    # a few microseconds of queue time between kernels.
+    flops = {"born_pair": FLOP_BORN, "energy_pair": FLOP_ENERGY, "chain_pair": FLOP_CHAIN}
+    dom = max(tuned["ms"], key=lambda k: tuned["ms"][k])
+    _progress(f"timing {K} steps (events on {dom})")
+    ctx.set_timing(not args.graph, (dom,))
     ctx.get_timing()                       # reset
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -164,24 +173,31 @@ def main():
 
     value = K * n_pairs / dt
     ms_step = 1000.0 * dt / K
-    # dominant pair kernel
-    flops = {"born_pair": FLOP_BORN, "energy_pair": FLOP_ENERGY, "chain_pair": FLOP_CHAIN}
-    per_kernel = {}
-    for k in flops:
-        ms, cnt = timing.get(k, (0.0, 0))
-        if cnt:
-            avg = ms / cnt
-            per_kernel[k] = {"avg_ms": avg, "launches": cnt,
-                             "tflops": flops[k] * n_pairs / (avg * 1e-3) / 1e12}
-    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"]) if per_kernel else None
     roofline = None
-    if dom:
-        ach = per_kernel[dom]["tflops"]
+    ms, cnt = timing.get(dom, (0.0, 0))
+    if cnt:
+        avg = ms / cnt
+        ach = flops[dom] * n_pairs / (avg * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
                     "traffic": traffic_from_profile(dom, None),
-                    "avg_launch_ms": per_kernel[dom]["avg_ms"],
+                    "avg_launch_ms": avg, "launches": cnt,
                     "flop_per_pair": flops[dom], "pairs_per_launch": n_pairs}
+    # the three pair passes side by side, from a short run after the timed region
+    n_break = 20
+    ctx.set_timing(True, tuple(flops))
+    ctx.get_timing()
+    md.run(n_break)
+    torch.cuda.synchronize()
+    tb = ctx.get_timing()
+    ctx.set_timing(False)
+    per_kernel = {}
+    for k in flops:
+        ms_k, cnt_k = tb.get(k, (0.0, 0))
+        if cnt_k:
+            avg_k = ms_k / cnt_k
+            per_kernel[k] = {"avg_ms": avg_k, "launches": cnt_k,
+                             "tflops": flops[k] * n_pairs / (avg_k * 1e-3) / 1e12}
     pair_ms = sum(v["avg_ms"] for v in per_kernel.values())
     all_pairs_tflops = FLOP_PAIR * n_pairs / (pair_ms * 1e-3) / 1e12 if pair_ms else None
 
@@ -252,6 +268,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "pair_kernels": per_kernel,
+        "pair_kernels_note": f"all three passes timed with events over {n_break} steps after the timed region",
         "all_pair_passes_tflops": all_pairs_tflops,
         "eval": evals,
         "paper_context": PAPER_CONTEXT,

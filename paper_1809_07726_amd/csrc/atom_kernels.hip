@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_born_finalize(
     double alpha, double beta, double gamma, float* __restrict__ R, float* __restrict__ dRdpsi,
     double* __restrict__ psi_out, uint32_t* __restrict__ err)
 {
-    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
     const int lane = threadIdx.x & 63;
     const int2 tl = tiles[t];
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_coef(
     double offset, double* __restrict__ dEdR, float* __restrict__ cc,
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
-    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
     const int lane = threadIdx.x & 63;
     const int2 tl = tiles[t];

@@ -53,6 +53,12 @@ __device__ __forceinline__ double from_fixed(int64_t v, double inv_scale) {
 }
 
 // -------------------------------------------------------- wave reductions
+// Index of the calling wavefront inside its workgroup, as a wave-uniform
+// value: loads indexed by it (work items, replica offsets) become scalar loads.
+__device__ __forceinline__ int wave_in_group() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
     // doubles: butterfly through shuffles (used only once per tile)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, GBR_WAVE);

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_md_first(
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ psi_fx,
     int64_t* __restrict__ dEdR_fx, int64_t* __restrict__ ke_fx, double* __restrict__ ke)
 {
-    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
     const int lane = threadIdx.x & 63;
     const int2 tl = tiles[t];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_md_last(
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx,
     uint64_t* __restrict__ step, int kick, uint32_t* __restrict__ err)
 {
-    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
     const int lane = threadIdx.x & 63;
     const int2 tl = tiles[t];

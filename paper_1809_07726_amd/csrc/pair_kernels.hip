@@ -43,7 +43,7 @@ constexpr float LOG2E = 1.4426950408889634f;
 __device__ __forceinline__ int logical_wave() {
     const int nb = gridDim.x, b = blockIdx.x;
     const int lb = (nb & 7) ? b : ((b & 7) * (nb >> 3) + (b >> 3));
-    return lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    return lb * (blockDim.x >> 6) + wave_in_group();
 }
 
 // acc <- acc[lane + 1 (mod 64)] + c : rotate-and-add, one VALU instruction.
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
     uint32_t* __restrict__ err)
 {
     __shared__ float4 lds[MAXW][2][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
     for (int it = logical_wave(); it < n_items; it += stride) {
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
     __shared__ float4 lds[MAXW][2][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float lc = 0.60056120439322491f;       // sqrt(log2(e) / 4)
     const float hl = 0.5f / LOG2E;               // D = D2 / log2(e)
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdrho_fx, uint32_t* __restrict__ err)
 {
     __shared__ float4 lds[MAXW][3][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
     for (int it = logical_wave(); it < n_items; it += stride) {

@@ -3,7 +3,8 @@
 Times the three pair passes (descreening, energy, chain rule) on the caller's
 own batch for every register blocking (i atoms per lane: 1, 2, 4, 8) and a set
 of launch shapes (wavefronts per workgroup x workgroups per CU of the
-persistent grid), using the library's HIP-event kernel timers, and installs
+persistent grid), using the library's HIP-event kernel timers after a short
+warm-up (device clocks ramp up under sustained load), and installs
 the fastest combination in the context: per pass the fastest blocking, and the
 launch shape whose summed pass time is lowest.  Results can be cached in a JSON
 file keyed by the device architecture and the batch's replica sizes.
@@ -43,7 +44,20 @@ def _time_eval(ctx, t, reps):
     return {k: tm[k][0] / max(tm[k][1], 1) for k in PASSES}
 
 
-def autotune(ctx, t: dict, reps: int = 3, shapes=SHAPES, blockings=BLOCKINGS,
+def _warm(ctx, t, ms=50.0):
+    """Runs evaluations for about `ms` milliseconds so that the device clocks
+    have ramped up before anything is timed."""
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(10):
+            R, dR, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"], want_psi=False)
+            ctx.energy_forces(t["xyz"], t["q"], t["rho"], t["screen"], t["sigma"], t["eps"], R, dR)
+        torch.cuda.synchronize()
+
+
+def autotune(ctx, t: dict, reps: int = 10, shapes=SHAPES, blockings=BLOCKINGS,
              cache: str | None = None) -> dict:
     """Tune ctx for the inputs in t (the DeviceBatch tensors); returns
     {"shape": (wpg, gpc), "blocking": (ni_born, ni_energy, ni_chain),
@@ -57,6 +71,7 @@ def autotune(ctx, t: dict, reps: int = 3, shapes=SHAPES, blockings=BLOCKINGS,
             ctx.set_blocking(*best["blocking"])
             best["cached"] = True
             return best
+    _warm(ctx, t)
     table = []
     for shape in shapes:
         ctx.set_launch(*shape)
