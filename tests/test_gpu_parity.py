@@ -63,6 +63,24 @@ def test_every_register_blocking(ni):
     _check(b, gpu_eval(b, True, True, blocking=(ni, ni, ni)), _oracle_batch(b), grads=True)
 
 
+@pytest.mark.parametrize("ni", [1, 2])
+def test_launch_shapes_are_bitwise_identical(ni):
+    """One wavefront per workgroup or four, few or many workgroups per CU: each
+    item's partial sums do not depend on which wavefront runs it and the
+    fixed-point atomics are order-independent, so every shape gives the same
+    bits; one of them is checked against the oracle."""
+    b = synth.make_config(1, n_atoms=700, n_rep=3, per_replica_jitter=True)
+    ref = None
+    for shape in ((1, 1), (1, 32), (2, 32), (4, 8), (4, 32)):
+        g = gpu_eval(b, True, True, blocking=(ni, ni, ni), launch=shape)
+        if ref is None:
+            ref = g
+            _check(b, g, _oracle_batch(b), grads=True)
+            continue
+        for k in ("F_fx", "E_fx", "R", "dEdq", "dEdrho"):
+            assert np.array_equal(g[k], ref[k]), (shape, k)
+
+
 def test_bitwise_reproducible_and_newton_balanced():
     b = synth.make_config(2, n_rep=4, per_replica_jitter=True)
     g1 = gpu_eval(b, True, True)
