@@ -8,11 +8,13 @@ exchange attempt every 100 steps, all on the device.  A step processes
 192 * 1024 * 1023 / 2 = 100,564,992 pair interactions.
 
 Prints one JSON line (see the keys below).  Timing: W untimed warm-up steps,
-then K steps between two synchronizations.  The pair kernels are timed
-individually with HIP events recorded by the library on the launch stream
-inside the timed region; the dominant one gives the roofline entry.
+then K steps between two synchronizations.  Inside the timed region the
+library records HIP events on the launch stream around every launch of the
+dominant pair kernel (the slowest pass in the autotuner's timing), which gives
+the roofline entry; the three passes side by side come from a short run after
+the timed region.
 
---gpus N with N > 1 is refused: this build runs on one GPU.
+--gpus N with N > 1 is refused: the batch runs on one GPU.
 """
 import argparse
 import hashlib
@@ -119,8 +121,8 @@ def _progress(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "--gpus must be 1: the replica batch runs on one GPU "
+                                   "and is not sharded across GPUs"}))
         sys.exit(2)
     import torch
     from paper_1809_07726_amd import synth

@@ -1,5 +1,5 @@
 """Python layer over the C ABI: a context bound to one batch layout, device
-copies of a batch, the autograd Function, and the REMD driver.
+copies of a batch, the autograd Function, and the md_step wrapper (MD).
 
 Torch provides device memory and streams; every computation is a call into
 libgbremd.so (HIP kernels).  Results come back as torch tensors.
