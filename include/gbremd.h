@@ -22,8 +22,10 @@
  *     gbr_last_error() returns a thread-local message for the last failure.
  *   - Arrays passed in are owned by the caller; unless stated otherwise they
  *     are DEVICE pointers (hipMalloc / torch CUDA tensors) on the context's
- *     device.  The library never frees or reallocates caller memory.  It owns
- *     only the opaque gbr_ctx (workspace, work lists, graphs, timers).
+ *     device, and every call taking a context must be made with that device
+ *     current (otherwise GBR_E_INVAL, nothing launched).  The library never
+ *     frees or reallocates caller memory.  It owns only the opaque gbr_ctx
+ *     (workspace, work lists, graphs, timers).
  *   - All compute entry points are asynchronous on the caller's stream; only
  *     gbr_check, gbr_get_timing and gbr_ctx_destroy synchronize.
  *   - Host-checkable argument errors return GBR_E_INVAL before anything is

@@ -77,6 +77,10 @@ struct Timed {
 
 int check_ctx(const gbr_ctx* c) {
     if (!c) return fail(GBR_E_INVAL, "null context");
+    // launching on another device with this context's pointers would fault
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+        return fail(GBR_E_INVAL, "the context belongs to device %d but device %d is current", c->device, dev);
     return GBR_OK;
 }
 
@@ -305,7 +309,12 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
 
 int gbr_ctx_destroy(gbr_ctx* c) {
     if (!c) return GBR_OK;
+    // wait for and free on the context's own device, whatever the caller has current
+    int prev = -1;
+    const bool have_prev = hipGetDevice(&prev) == hipSuccess;
+    if (!have_prev || prev != c->device) (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    const int c_dev = c->device;
     for (auto& g : c->graph) if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& ev : c->timer.pool) if (ev) (void)hipEventDestroy(ev);
@@ -316,6 +325,7 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     (void)hipFree(c->ke_fx); (void)hipFree(c->ex_nH); (void)hipFree(c->ex_ne); (void)hipFree(c->ex_eps);
     (void)hipFree(c->ex_vscale); (void)hipFree(c->step); (void)hipFree(c->err);
     delete c;
+    if (have_prev && prev != c_dev) (void)hipSetDevice(prev);
     return GBR_OK;
 }
 
