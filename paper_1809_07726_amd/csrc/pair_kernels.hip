@@ -62,25 +62,46 @@ struct ItemGeom {
     int rep, a0, n, ibase, jbase, nj;
     int u_lim;      // i sub-blocks with a valid pair
     bool tri;       // triangle item (NI = 1 only)
-    int ksteps;     // steps of the item
+    bool diag;      // diagonal item of a two-tile block (NI = 2 only)
+    int phase;      // diagonal item: 0 = both tiles' own pairs, 1 = the cross pairs
+    int ksteps;     // rotation steps of the item
 };
 
 template <int NI>
 __device__ __forceinline__ ItemGeom item_geom(const int2 wi, const int32_t* __restrict__ atom_off) {
     ItemGeom g;
     g.rep = wi.x & 0x3FFFFFFF;
+    const int type = (int)((unsigned)wi.x >> 30);
     const int A = wi.y >> 16, B = wi.y & 0xFFFF;
     g.a0 = atom_off[g.rep];
     g.n = atom_off[g.rep + 1] - g.a0;
-    g.ibase = A * 64 * NI;
-    g.jbase = B * 64;
-    g.nj = min(64, g.n - g.jbase);
-    g.tri = NI == 1 && ((unsigned)wi.x >> 30) == ITEM_TRIANGLE;
-    g.ksteps = g.tri ? 32 : 64;
-    // I sub-blocks u with a valid pair: ibase + 64u < jbase + nj (and < n)
-    const int span = g.jbase + g.nj - g.ibase;
-    g.u_lim = min(NI, (span + 63) >> 6);
+    g.tri = NI == 1 && type == ITEM_TRIANGLE;
+    g.diag = NI == 2 && type == ITEM_DIAG;
+    if (NI == 2 && g.diag) {
+        g.phase = B;
+        g.ibase = A * 128;                              // tile a; tile b follows it
+        g.jbase = g.phase ? g.ibase + 64 : g.ibase;     // tile of LDS slot 0
+        g.nj = min(64, g.n - g.jbase);
+        g.u_lim = g.ibase + 64 < g.n ? 2 : 1;           // tile b exists
+        g.ksteps = 32;
+    } else {
+        g.phase = 0;
+        g.ibase = A * 64 * NI;
+        g.jbase = B * 64;
+        g.nj = min(64, g.n - g.jbase);
+        g.ksteps = g.tri ? 32 : 64;
+        // I sub-blocks u with a valid pair: ibase + 64u < jbase + nj (and < n)
+        const int span = g.jbase + g.nj - g.ibase;
+        g.u_lim = min(NI, (span + 63) >> 6);
+    }
     return g;
+}
+
+// i atom of sub-block u (the cross phase of a diagonal item holds tile a in
+// both sub-blocks).
+template <int NI>
+__device__ __forceinline__ int item_li(const ItemGeom& g, int u, int lane) {
+    return (NI == 2 && g.diag && g.phase == 1) ? g.ibase + lane : g.ibase + u * 64 + lane;
 }
 
 // Validity of the pair of sub-block u in the masked loop (step k, j tile slot
@@ -93,10 +114,10 @@ __device__ __forceinline__ bool pair_ok(const ItemGeom& g, int lane, int k, int 
     return jok & (li < g.jbase + m);
 }
 
-// Runs an item through the step loop kloop(full, k0, k1): the unmasked loop
-// for a block item that lies entirely before a full j tile, and for the first
-// 31 steps of a triangle on a full tile; the masked loop for the rest.  Each
-// variant is called from one place so that it is inlined.
+// Runs the item's steps through kloop(full, k0, k1): unmasked where every pair
+// is valid (a block item entirely before a full j tile; steps 0..30 of a
+// triangle on a full tile), masked for the rest.  Each variant is called from
+// one place so that it is inlined.
 template <int NI, typename K>
 __device__ __forceinline__ void run_item(const ItemGeom& g, K& kloop) {
     if constexpr (NI == 1) {
@@ -107,6 +128,30 @@ __device__ __forceinline__ void run_item(const ItemGeom& g, K& kloop) {
     } else {
         if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{}, 0, 64);
         else kloop(std::false_type{}, 0, 64);
+    }
+}
+
+// Diagonal item of a two-tile block (tiles a, b; NI = 2), two independent
+// sub-tasks per step so that a wavefront keeps two pairs in flight:
+//   phase 0: sub-task 0 = the pairs inside tile a, sub-task 1 = inside tile b,
+//            each as a triangle (32 steps, step 31 on lanes 0..31 only), j from
+//            LDS slots 0 (tile a) and 1 (tile b);
+//   phase 1: the cross pairs a x b, sub-task 0 taking rotation steps 0..31 and
+//            sub-task 1 steps 32..63, both with j from slot 0 (tile b).
+// step(m0, m1, ok0, ok1) receives each sub-task's j slot index and validity.
+// After the 32 steps sub-task u's j accumulators sit at j = (l + 32 + o_u) mod
+// 64 of their tile, o_1 = 32 in phase 1 and 0 otherwise.
+template <typename F>
+__device__ __forceinline__ void run_diag(const ItemGeom& g, int lane, F&& step) {
+    const int o1 = g.phase ? 32 : 0;
+    const int na = min(64, g.n - g.ibase), nb = min(64, g.n - g.ibase - 64);
+    const int nt0 = g.phase ? nb : na;
+    for (int k = 0; k < 32; ++k) {
+        const int m0 = (lane + k + 1) & 63, m1 = (lane + k + o1 + 1) & 63;
+        const bool own = (k < 31) | (lane < 32);
+        const bool ok0 = (m0 < nt0) & (g.phase | ((lane < nt0) & own));
+        const bool ok1 = (m1 < nb) & (g.phase | ((lane < nb) & own));
+        step(m0, m1, ok0, ok1);
     }
 }
 
@@ -128,7 +173,8 @@ __global__ __launch_bounds__(256) void k_born_pair(
     const float* __restrict__ screen, float offset, int64_t* __restrict__ psi_fx,
     uint32_t* __restrict__ err)
 {
-    __shared__ float4 lds[MAXW][2][64];
+    constexpr int NSL = NI == 2 ? 2 : 1;           // j tiles per wavefront
+    __shared__ float4 lds[MAXW][NSL][2][64];
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
@@ -138,7 +184,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
         int li[NI];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            li[u] = g.ibase + u * 64 + lane;
+            li[u] = item_li<NI>(g, u, lane);
             const int a = g.a0 + min(li[u], g.n - 1);
             xi[u] = xyz[a]; yi[u] = xyz[ntot + a]; zi[u] = xyz[2 * ntot + a];
             rti[u] = rho[a] - offset;
@@ -149,52 +195,81 @@ __global__ __launch_bounds__(256) void k_born_pair(
             sxi[u] = si[u] * ixmax;
             acc[u] = 0.0f;
         }
-        {
-            const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
+        auto fill = [&](int slot, int tb) {
+            const int ja = g.a0 + min(tb + lane, g.n - 1);
             const float rt = rho[ja] - offset, s = screen[ja] * rt;
-            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s);
-            lds[wv][1][lane] = make_float4(rt, fmaxf(rt, s), s * ixmax, s * s * s);
-        }
+            lds[wv][slot][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s);
+            lds[wv][slot][1][lane] = make_float4(rt, fmaxf(rt, s), s * ixmax, s * s * s);
+        };
+        fill(0, g.jbase);
+        if (NSL > 1 && g.diag && g.phase == 0 && g.u_lim > 1) fill(NSL - 1, g.ibase + 64);
         wave_lds_fence();
-        float accj = 0.0f;
+        float accj[NSL];
+#pragma unroll
+        for (int t = 0; t < NSL; ++t) accj[t] = 0.0f;
+        // sub-block u against j data (p0, p1): adds h_ij to i, returns h_ji
+        auto pair = [&](int u, const float4& p0, const float4& p1, bool ok, auto full) -> float {
+            constexpr bool FULL = decltype(full)::value;
+            const float sj = p0.w, s2j = sj * sj;
+            const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+            float r2 = dx * dx + dy * dy + dz * dz;
+            if (!FULL) r2 = ok ? r2 : FAR_R2;
+            const float rinv = frsq(r2);
+            const float rinv2 = rinv * rinv;
+            const float rinv4 = rinv2 * rinv2;
+            float hij = (p1.w * rinv4) * poly_G(s2j * rinv2);
+            float hji = (s3i[u] * rinv4) * poly_G(s2i[u] * rinv2);
+            const float r = r2 * rinv;
+            if (!both_far(r, mi[u], p1.y, sxi[u], p1.z)) {
+                hij = (r + sj <= rti[u]) ? 0.0f : hct_closed(r, rinv, rti[u], sj);
+                hji = (r + si[u] <= p1.x) ? 0.0f : hct_closed(r, rinv, p1.x, si[u]);
+            }
+            acc[u] += hij;
+            return hji;
+        };
         auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
             for (int k = k0; k < k1; ++k) {
                 const int m = (lane + k + 1) & 63;
-                const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
-                const float sj = p0.w, s2j = sj * sj;
+                const float4 p0 = lds[wv][0][0][m], p1 = lds[wv][0][1][m];
                 float cj = 0.0f;
 #pragma unroll
                 for (int u = 0; u < NI; ++u) {
                     if (FULL || u < g.u_lim) {
-                        const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
-                        float r2 = dx * dx + dy * dy + dz * dz;
-                        if (!FULL) r2 = pair_ok<NI>(g, lane, k, m, li[u]) ? r2 : FAR_R2;
-                        const float rinv = frsq(r2);
-                        const float rinv2 = rinv * rinv;
-                        const float rinv4 = rinv2 * rinv2;
-                        float hij = (p1.w * rinv4) * poly_G(s2j * rinv2);
-                        float hji = (s3i[u] * rinv4) * poly_G(s2i[u] * rinv2);
-                        const float r = r2 * rinv;
-                        if (!both_far(r, mi[u], p1.y, sxi[u], p1.z)) {
-                            hij = (r + sj <= rti[u]) ? 0.0f : hct_closed(r, rinv, rti[u], sj);
-                            hji = (r + si[u] <= p1.x) ? 0.0f : hct_closed(r, rinv, p1.x, si[u]);
-                        }
-                        acc[u] += hij;
-                        cj = (u == 0) ? hji : cj + hji;
+                        const float h = pair(u, p0, p1, FULL || pair_ok<NI>(g, lane, k, m, li[u]), full);
+                        cj = (u == 0) ? h : cj + h;
                     }
                 }
-                accj = rot_add(accj, cj);
+                accj[0] = rot_add(accj[0], cj);
             }
         };
-        run_item<NI>(g, kloop);
+        if constexpr (NI == 2) {
+            if (g.diag) {
+                const int s1 = g.phase ? 0 : NSL - 1;
+                run_diag(g, lane, [&](int m0, int m1, bool ok0, bool ok1) {
+                    accj[0] = rot_add(accj[0], pair(0, lds[wv][0][0][m0], lds[wv][0][1][m0], ok0,
+                                                    std::false_type{}));
+                    if (g.u_lim > 1)
+                        accj[NSL - 1] = rot_add(accj[NSL - 1], pair(1, lds[wv][s1][0][m1], lds[wv][s1][1][m1],
+                                                                    ok1, std::false_type{}));
+                });
+            } else {
+                run_item<NI>(g, kloop);
+            }
+        } else {
+            run_item<NI>(g, kloop);
+        }
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u)
-            if (li[u] < g.n)
+            if (u < g.u_lim && li[u] < g.n)
                 atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed(acc[u], FX_FORCE, err));
         const int jl = g.jbase + ((lane + g.ksteps) & 63);
-        if (jl < g.n) atomic_add_fx(&psi_fx[g.a0 + jl], to_fixed(accj, FX_FORCE, err));
+        if (jl < g.n) atomic_add_fx(&psi_fx[g.a0 + jl], to_fixed(accj[0], FX_FORCE, err));
+        if (NSL > 1 && g.diag && g.u_lim > 1) {
+            const int jl1 = g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63);
+            if (jl1 < g.n) atomic_add_fx(&psi_fx[g.a0 + jl1], to_fixed(accj[NSL - 1], FX_FORCE, err));
+        }
     }
 }
 
@@ -210,6 +285,10 @@ __global__ __launch_bounds__(256) void k_born_pair(
 //   dE/dq_i = sqrt(k_e/eps_in) (1/r - tau'/f) qc_j
 // The factors tau' and sqrt(k_e/eps_in) are applied once per atom at the flush.
 // j tile in LDS: {x, y, z, qc}, {R, L2, hs, se}.
+struct EnergyJ {
+    float x, y, z, R, q;
+};
+
 template <int NI, bool GQ>
 __global__ __launch_bounds__(256) void k_energy_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
@@ -218,7 +297,8 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdR_fx,
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
-    __shared__ float4 lds[MAXW][2][64];
+    constexpr int NSL = NI == 2 ? 2 : 1;
+    __shared__ float4 lds[MAXW][NSL][2][64];
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float lc = 0.60056120439322491f;       // sqrt(log2(e) / 4)
@@ -231,7 +311,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         int li[NI];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            li[u] = g.ibase + u * 64 + lane;
+            li[u] = item_li<NI>(g, u, lane);
             const int a = g.a0 + min(li[u], g.n - 1);
             xi[u] = xyz[a]; yi[u] = xyz[ntot + a]; zi[u] = xyz[2 * ntot + a];
             qi[u] = q[a] * sq_ke_in;
@@ -241,81 +321,109 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             sei[u] = 2.0f * sqrtf(eps[a]);
             fxi[u] = fyi[u] = fzi[u] = dRi[u] = dqi[u] = 0.0f;
         }
-        {
-            const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
+        auto fill = [&](int slot, int tb) {
+            const int ja = g.a0 + min(tb + lane, g.n - 1);
             const float Rj = Rb[ja];
-            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], q[ja] * sq_ke_in);
-            lds[wv][1][lane] = make_float4(Rj, lc / Rj, 0.5f * sigma[ja], 2.0f * sqrtf(eps[ja]));
-        }
+            lds[wv][slot][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], q[ja] * sq_ke_in);
+            lds[wv][slot][1][lane] = make_float4(Rj, lc / Rj, 0.5f * sigma[ja], 2.0f * sqrtf(eps[ja]));
+        };
+        fill(0, g.jbase);
+        if (NSL > 1 && g.diag && g.phase == 0 && g.u_lim > 1) fill(NSL - 1, g.ibase + 64);
         wave_lds_fence();
-        float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, dRj = 0.0f, dqj = 0.0f;
+        EnergyJ accj[NSL];
+#pragma unroll
+        for (int t = 0; t < NSL; ++t) accj[t] = EnergyJ{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         float e_c = 0.0f, e_g = 0.0f, e_lj = 0.0f;
+        // sub-block u against j data (p0, p1): i-side sums, and the j-side terms
+        // written (first) or added into c
+        auto pair = [&](int u, const float4& p0, const float4& p1, bool ok, auto full, EnergyJ& c, bool first) {
+            constexpr bool FULL = decltype(full)::value;
+            const bool valid = FULL || ok;
+            const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float rinv = valid ? frsq(r2) : 0.0f;
+            const float rinv2 = rinv * rinv;
+            const float qq = qi[u] * p0.w;
+            const float ec = qq * rinv;
+            const float D2 = r2 * (Li[u] * p1.y);          // D log2(e)
+            const float ex = __builtin_amdgcn_exp2f(-D2);   // exp(-D)
+            const float f2 = __builtin_fmaf(Ri[u] * p1.x, ex, r2);
+            const float finv = valid ? frsq(f2) : 0.0f;
+            const float eg = qq * finv;
+            const float t = eg * finv * finv;               // qq / f^3
+            const float sgr = (hsi[u] + p1.z) * rinv;
+            const float s2 = sgr * sgr;
+            const float s6 = s2 * s2 * s2;
+            const float A = (sei[u] * p1.w) * s6;           // 4 eps_ij s^6
+            const float B = A * s6;                         // 4 eps_ij s^12
+            const float elj = B - A;
+            const float uu = __builtin_fmaf(6.0f, B + elj, ec);
+            const float w = __builtin_fmaf(ex, wq, taup);   // tau' (1 - exp(-D)/4)
+            const float fs = __builtin_fmaf(-uu, rinv2, t * w);
+            const float gR = t * ex * __builtin_fmaf(D2, hl, 0.5f);
+            e_c += ec;
+            e_g += eg;
+            e_lj += elj;
+            fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
+            fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
+            fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
+            dRi[u] = __builtin_fmaf(gR, p1.x, dRi[u]);
+            if (first) {
+                c.x = -fs * dx; c.y = -fs * dy; c.z = -fs * dz; c.R = gR * Ri[u];
+            } else {
+                c.x = __builtin_fmaf(-fs, dx, c.x);
+                c.y = __builtin_fmaf(-fs, dy, c.y);
+                c.z = __builtin_fmaf(-fs, dz, c.z);
+                c.R = __builtin_fmaf(gR, Ri[u], c.R);
+            }
+            if (GQ) {
+                const float wqq = __builtin_fmaf(-taup, finv, rinv);
+                dqi[u] = __builtin_fmaf(wqq, p0.w, dqi[u]);
+                c.q = first ? wqq * qi[u] : __builtin_fmaf(wqq, qi[u], c.q);
+            }
+        };
+        auto rotate = [&](EnergyJ& a, const EnergyJ& c) {
+            a.x = rot_add(a.x, c.x);
+            a.y = rot_add(a.y, c.y);
+            a.z = rot_add(a.z, c.z);
+            a.R = rot_add(a.R, c.R);
+            if (GQ) a.q = rot_add(a.q, c.q);
+        };
         auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
             for (int k = k0; k < k1; ++k) {
                 const int m = (lane + k + 1) & 63;
-                const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m];
-                float cx = 0.0f, cy = 0.0f, cz = 0.0f, cR = 0.0f, cq = 0.0f;
+                const float4 p0 = lds[wv][0][0][m], p1 = lds[wv][0][1][m];
+                EnergyJ c{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int u = 0; u < NI; ++u) {
-                    if (FULL || u < g.u_lim) {
-                        const bool valid = FULL || pair_ok<NI>(g, lane, k, m, li[u]);
-                        const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        const float rinv = valid ? frsq(r2) : 0.0f;
-                        const float rinv2 = rinv * rinv;
-                        const float qq = qi[u] * p0.w;
-                        const float ec = qq * rinv;
-                        const float D2 = r2 * (Li[u] * p1.y);          // D log2(e)
-                        const float ex = __builtin_amdgcn_exp2f(-D2);   // exp(-D)
-                        const float f2 = __builtin_fmaf(Ri[u] * p1.x, ex, r2);
-                        const float finv = valid ? frsq(f2) : 0.0f;
-                        const float eg = qq * finv;
-                        const float t = eg * finv * finv;               // qq / f^3
-                        const float sgr = (hsi[u] + p1.z) * rinv;
-                        const float s2 = sgr * sgr;
-                        const float s6 = s2 * s2 * s2;
-                        const float A = (sei[u] * p1.w) * s6;           // 4 eps_ij s^6
-                        const float B = A * s6;                         // 4 eps_ij s^12
-                        const float elj = B - A;
-                        const float uu = __builtin_fmaf(6.0f, B + elj, ec);
-                        const float w = __builtin_fmaf(ex, wq, taup);   // tau' (1 - exp(-D)/4)
-                        const float fs = __builtin_fmaf(-uu, rinv2, t * w);
-                        const float gR = t * ex * __builtin_fmaf(D2, hl, 0.5f);
-                        e_c += ec;
-                        e_g += eg;
-                        e_lj += elj;
-                        fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
-                        fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
-                        fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
-                        dRi[u] = __builtin_fmaf(gR, p1.x, dRi[u]);
-                        if (u == 0) {
-                            cx = -fs * dx; cy = -fs * dy; cz = -fs * dz; cR = gR * Ri[u];
-                        } else {
-                            cx = __builtin_fmaf(-fs, dx, cx);
-                            cy = __builtin_fmaf(-fs, dy, cy);
-                            cz = __builtin_fmaf(-fs, dz, cz);
-                            cR = __builtin_fmaf(gR, Ri[u], cR);
-                        }
-                        if (GQ) {
-                            const float wqq = __builtin_fmaf(-taup, finv, rinv);
-                            dqi[u] = __builtin_fmaf(wqq, p0.w, dqi[u]);
-                            cq = (u == 0) ? wqq * qi[u] : __builtin_fmaf(wqq, qi[u], cq);
-                        }
-                    }
-                }
-                fxj = rot_add(fxj, cx);
-                fyj = rot_add(fyj, cy);
-                fzj = rot_add(fzj, cz);
-                dRj = rot_add(dRj, cR);
-                if (GQ) dqj = rot_add(dqj, cq);
+                for (int u = 0; u < NI; ++u)
+                    if (FULL || u < g.u_lim)
+                        pair(u, p0, p1, FULL || pair_ok<NI>(g, lane, k, m, li[u]), full, c, u == 0);
+                rotate(accj[0], c);
             }
         };
-        run_item<NI>(g, kloop);
+        if constexpr (NI == 2) {
+            if (g.diag) {
+                const int s1 = g.phase ? 0 : NSL - 1;
+                run_diag(g, lane, [&](int m0, int m1, bool ok0, bool ok1) {
+                    EnergyJ c0{0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, c1{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                    pair(0, lds[wv][0][0][m0], lds[wv][0][1][m0], ok0, std::false_type{}, c0, true);
+                    rotate(accj[0], c0);
+                    if (g.u_lim > 1) {
+                        pair(1, lds[wv][s1][0][m1], lds[wv][s1][1][m1], ok1, std::false_type{}, c1, true);
+                        rotate(accj[NSL - 1], c1);
+                    }
+                });
+            } else {
+                run_item<NI>(g, kloop);
+            }
+        } else {
+            run_item<NI>(g, kloop);
+        }
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            if (li[u] < g.n) {
+            if (u < g.u_lim && li[u] < g.n) {
                 const int a = g.a0 + li[u];
                 atomic_add_fx(&force_fx[a], to_fixed(fxi[u], FX_FORCE, err));
                 atomic_add_fx(&force_fx[ntot + a], to_fixed(fyi[u], FX_FORCE, err));
@@ -324,15 +432,18 @@ __global__ __launch_bounds__(256) void k_energy_pair(
                 if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)dqi[u] * sq_ke_in, FX_FORCE, err));
             }
         }
-        const int jl = g.jbase + ((lane + g.ksteps) & 63);
-        if (jl < g.n) {
+        auto flush_j = [&](int jl, const EnergyJ& aj) {
+            if (jl >= g.n) return;
             const int a = g.a0 + jl;
-            atomic_add_fx(&force_fx[a], to_fixed(fxj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[ntot + a], to_fixed(fyj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzj, FX_FORCE, err));
-            atomic_add_fx(&dEdR_fx[a], to_fixed((double)dRj * taup, FX_FORCE, err));
-            if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)dqj * sq_ke_in, FX_FORCE, err));
-        }
+            atomic_add_fx(&force_fx[a], to_fixed(aj.x, FX_FORCE, err));
+            atomic_add_fx(&force_fx[ntot + a], to_fixed(aj.y, FX_FORCE, err));
+            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(aj.z, FX_FORCE, err));
+            atomic_add_fx(&dEdR_fx[a], to_fixed((double)aj.R * taup, FX_FORCE, err));
+            if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)aj.q * sq_ke_in, FX_FORCE, err));
+        };
+        flush_j(g.jbase + ((lane + g.ksteps) & 63), accj[0]);
+        if (NSL > 1 && g.diag && g.u_lim > 1)
+            flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
         const double sgb = wave_sum_d(-(double)taup * (double)e_g);
         const double sc = wave_sum_d((double)e_c);
         const double slj = wave_sum_d((double)e_lj);
@@ -351,6 +462,10 @@ __global__ __launch_bounds__(256) void k_energy_pair(
 // With RHO also the pair part of dE/drho:
 //   i: c_i dh_ij/drt + S_i c_j dh_ji/ds,   j: c_j dh_ji/drt + S_j c_i dh_ij/ds.
 // j tile in LDS: {x, y, z, c}, {rt, s, m, sx}, {s^2, s^3, S, -}.
+struct ChainJ {
+    float x, y, z, r;
+};
+
 template <int NI, bool RHO>
 __global__ __launch_bounds__(256) void k_chain_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
@@ -358,7 +473,8 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     const float* __restrict__ screen, const float* __restrict__ cc, float offset,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdrho_fx, uint32_t* __restrict__ err)
 {
-    __shared__ float4 lds[MAXW][3][64];
+    constexpr int NSL = NI == 2 ? 2 : 1;
+    __shared__ float4 lds[MAXW][NSL][3][64];
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
@@ -369,7 +485,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
         int li[NI];
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            li[u] = g.ibase + u * 64 + lane;
+            li[u] = item_li<NI>(g, u, lane);
             const int a = g.a0 + min(li[u], g.n - 1);
             xi[u] = xyz[a]; yi[u] = xyz[ntot + a]; zi[u] = xyz[2 * ntot + a];
             rti[u] = rho[a] - offset;
@@ -382,71 +498,100 @@ __global__ __launch_bounds__(256) void k_chain_pair(
             s3i[u] = s2i[u] * si[u];
             fxi[u] = fyi[u] = fzi[u] = dri[u] = 0.0f;
         }
-        {
-            const int ja = g.a0 + min(g.jbase + lane, g.n - 1);
+        auto fill = [&](int slot, int tb) {
+            const int ja = g.a0 + min(tb + lane, g.n - 1);
             const float rt = rho[ja] - offset, S = screen[ja], s = S * rt;
-            lds[wv][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], cc[ja]);
-            lds[wv][1][lane] = make_float4(rt, s, fmaxf(rt, s), s * ixmax);
-            lds[wv][2][lane] = make_float4(s * s, s * s * s, S, 0.0f);
-        }
+            lds[wv][slot][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], cc[ja]);
+            lds[wv][slot][1][lane] = make_float4(rt, s, fmaxf(rt, s), s * ixmax);
+            lds[wv][slot][2][lane] = make_float4(s * s, s * s * s, S, 0.0f);
+        };
+        fill(0, g.jbase);
+        if (NSL > 1 && g.diag && g.phase == 0 && g.u_lim > 1) fill(NSL - 1, g.ibase + 64);
         wave_lds_fence();
-        float fxj = 0.0f, fyj = 0.0f, fzj = 0.0f, drj = 0.0f;
+        ChainJ accj[NSL];
+#pragma unroll
+        for (int t = 0; t < NSL; ++t) accj[t] = ChainJ{0.0f, 0.0f, 0.0f, 0.0f};
+        auto pair = [&](int u, const float4& p0, const float4& p1, const float4& p2, bool ok, auto full,
+                        ChainJ& c, bool first) {
+            constexpr bool FULL = decltype(full)::value;
+            const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
+            float r2 = dx * dx + dy * dy + dz * dz;
+            if (!FULL) r2 = ok ? r2 : FAR_R2;
+            const float rinv = frsq(r2);
+            const float r = r2 * rinv;
+            const float rinv2 = rinv * rinv;
+            float fs;
+            if (!RHO) {
+                const float Qij = poly_Q(p2.x * rinv2), Qji = poly_Q(s2i[u] * rinv2);
+                const float G = __builtin_fmaf(p0.w * s3i[u], Qji, ci[u] * (p2.y * Qij));
+                fs = -G * (rinv2 * rinv2 * rinv2);
+                if (!both_far(r, mi[u], p1.z, sxi[u], p1.w)) {
+                    const float dij = (r + p1.y <= rti[u]) ? 0.0f : hct_dr_closed(r, rinv, rti[u], p1.y);
+                    const float dji = (r + si[u] <= p1.x) ? 0.0f : hct_dr_closed(r, rinv, p1.x, si[u]);
+                    fs = (ci[u] * dij + p0.w * dji) * rinv;
+                }
+            } else {
+                float dr_ij, drt_ij, ds_ij, dr_ji, drt_ji, ds_ji;
+                hct_grad3(r, rinv, rti[u], p1.y, dr_ij, drt_ij, ds_ij);
+                hct_grad3(r, rinv, p1.x, si[u], dr_ji, drt_ji, ds_ji);
+                fs = (ci[u] * dr_ij + p0.w * dr_ji) * rinv;
+                dri[u] += ci[u] * drt_ij + Si[u] * p0.w * ds_ji;
+                const float cr = p0.w * drt_ji + p2.z * ci[u] * ds_ij;
+                c.r = first ? cr : c.r + cr;
+            }
+            fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
+            fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
+            fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
+            if (first) {
+                c.x = -fs * dx; c.y = -fs * dy; c.z = -fs * dz;
+            } else {
+                c.x = __builtin_fmaf(-fs, dx, c.x);
+                c.y = __builtin_fmaf(-fs, dy, c.y);
+                c.z = __builtin_fmaf(-fs, dz, c.z);
+            }
+        };
+        auto rotate = [&](ChainJ& a, const ChainJ& c) {
+            a.x = rot_add(a.x, c.x);
+            a.y = rot_add(a.y, c.y);
+            a.z = rot_add(a.z, c.z);
+            if (RHO) a.r = rot_add(a.r, c.r);
+        };
         auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
             for (int k = k0; k < k1; ++k) {
                 const int m = (lane + k + 1) & 63;
-                const float4 p0 = lds[wv][0][m], p1 = lds[wv][1][m], p2 = lds[wv][2][m];
-                float cx = 0.0f, cy = 0.0f, cz = 0.0f, cr = 0.0f;
+                const float4 p0 = lds[wv][0][0][m], p1 = lds[wv][0][1][m], p2 = lds[wv][0][2][m];
+                ChainJ c{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int u = 0; u < NI; ++u) {
-                    if (FULL || u < g.u_lim) {
-                        const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
-                        float r2 = dx * dx + dy * dy + dz * dz;
-                        if (!FULL) r2 = pair_ok<NI>(g, lane, k, m, li[u]) ? r2 : FAR_R2;
-                        const float rinv = frsq(r2);
-                        const float r = r2 * rinv;
-                        const float rinv2 = rinv * rinv;
-                        float fs;
-                        if (!RHO) {
-                            const float Qij = poly_Q(p2.x * rinv2), Qji = poly_Q(s2i[u] * rinv2);
-                            const float G = __builtin_fmaf(p0.w * s3i[u], Qji, ci[u] * (p2.y * Qij));
-                            fs = -G * (rinv2 * rinv2 * rinv2);
-                            if (!both_far(r, mi[u], p1.z, sxi[u], p1.w)) {
-                                const float dij = (r + p1.y <= rti[u]) ? 0.0f : hct_dr_closed(r, rinv, rti[u], p1.y);
-                                const float dji = (r + si[u] <= p1.x) ? 0.0f : hct_dr_closed(r, rinv, p1.x, si[u]);
-                                fs = (ci[u] * dij + p0.w * dji) * rinv;
-                            }
-                        } else {
-                            float dr_ij, drt_ij, ds_ij, dr_ji, drt_ji, ds_ji;
-                            hct_grad3(r, rinv, rti[u], p1.y, dr_ij, drt_ij, ds_ij);
-                            hct_grad3(r, rinv, p1.x, si[u], dr_ji, drt_ji, ds_ji);
-                            fs = (ci[u] * dr_ij + p0.w * dr_ji) * rinv;
-                            dri[u] += ci[u] * drt_ij + Si[u] * p0.w * ds_ji;
-                            cr += p0.w * drt_ji + p2.z * ci[u] * ds_ij;
-                        }
-                        fxi[u] = __builtin_fmaf(fs, dx, fxi[u]);
-                        fyi[u] = __builtin_fmaf(fs, dy, fyi[u]);
-                        fzi[u] = __builtin_fmaf(fs, dz, fzi[u]);
-                        if (u == 0) {
-                            cx = -fs * dx; cy = -fs * dy; cz = -fs * dz;
-                        } else {
-                            cx = __builtin_fmaf(-fs, dx, cx);
-                            cy = __builtin_fmaf(-fs, dy, cy);
-                            cz = __builtin_fmaf(-fs, dz, cz);
-                        }
-                    }
-                }
-                fxj = rot_add(fxj, cx);
-                fyj = rot_add(fyj, cy);
-                fzj = rot_add(fzj, cz);
-                if (RHO) drj = rot_add(drj, cr);
+                for (int u = 0; u < NI; ++u)
+                    if (FULL || u < g.u_lim)
+                        pair(u, p0, p1, p2, FULL || pair_ok<NI>(g, lane, k, m, li[u]), full, c, u == 0);
+                rotate(accj[0], c);
             }
         };
-        run_item<NI>(g, kloop);
+        if constexpr (NI == 2) {
+            if (g.diag) {
+                const int s1 = g.phase ? 0 : NSL - 1;
+                run_diag(g, lane, [&](int m0, int m1, bool ok0, bool ok1) {
+                    ChainJ c0{0.0f, 0.0f, 0.0f, 0.0f}, c1{0.0f, 0.0f, 0.0f, 0.0f};
+                    pair(0, lds[wv][0][0][m0], lds[wv][0][1][m0], lds[wv][0][2][m0], ok0, std::false_type{}, c0, true);
+                    rotate(accj[0], c0);
+                    if (g.u_lim > 1) {
+                        pair(1, lds[wv][s1][0][m1], lds[wv][s1][1][m1], lds[wv][s1][2][m1], ok1, std::false_type{},
+                             c1, true);
+                        rotate(accj[NSL - 1], c1);
+                    }
+                });
+            } else {
+                run_item<NI>(g, kloop);
+            }
+        } else {
+            run_item<NI>(g, kloop);
+        }
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            if (li[u] < g.n) {
+            if (u < g.u_lim && li[u] < g.n) {
                 const int a = g.a0 + li[u];
                 atomic_add_fx(&force_fx[a], to_fixed(fxi[u], FX_FORCE, err));
                 atomic_add_fx(&force_fx[ntot + a], to_fixed(fyi[u], FX_FORCE, err));
@@ -454,14 +599,17 @@ __global__ __launch_bounds__(256) void k_chain_pair(
                 if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(dri[u], FX_FORCE, err));
             }
         }
-        const int jl = g.jbase + ((lane + g.ksteps) & 63);
-        if (jl < g.n) {
+        auto flush_j = [&](int jl, const ChainJ& aj) {
+            if (jl >= g.n) return;
             const int a = g.a0 + jl;
-            atomic_add_fx(&force_fx[a], to_fixed(fxj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[ntot + a], to_fixed(fyj, FX_FORCE, err));
-            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzj, FX_FORCE, err));
-            if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(drj, FX_FORCE, err));
-        }
+            atomic_add_fx(&force_fx[a], to_fixed(aj.x, FX_FORCE, err));
+            atomic_add_fx(&force_fx[ntot + a], to_fixed(aj.y, FX_FORCE, err));
+            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(aj.z, FX_FORCE, err));
+            if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(aj.r, FX_FORCE, err));
+        };
+        flush_j(g.jbase + ((lane + g.ksteps) & 63), accj[0]);
+        if (NSL > 1 && g.diag && g.u_lim > 1)
+            flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
     }
 }
 

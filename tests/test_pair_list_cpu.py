@@ -43,22 +43,47 @@ def _items(exe, ni, sizes):
     return np.array([list(map(int, l.split())) for l in out.splitlines()], dtype=np.int64).reshape(-1, 4)
 
 
+def _rotation(lane, k):
+    return (lane + k + 1) & 63
+
+
 def _pairs_of_item(n, ni, typ, A, B):
     """Pairs (i, j) the kernels evaluate for one item, following their masks."""
     lane = np.arange(64)
-    nj = min(64, n - 64 * B)
+    out = []
     if typ == 0:                     # block: i in block A (inside the replica) x tile B, i < j
+        nj = min(64, n - 64 * B)
         i = 64 * ni * A + np.arange(64 * ni)
         i = i[i < n]
         j = 64 * B + np.arange(nj)
         P = np.stack(np.meshgrid(i, j, indexing="ij"), -1).reshape(-1, 2)
         return P[P[:, 0] < P[:, 1]]
-    assert typ == 2 and A == B and ni == 1      # triangle: 32 rotation steps
-    out = []
+    if typ == 2:                     # triangle (NI = 1): 32 rotation steps
+        assert A == B and ni == 1
+        nj = min(64, n - 64 * A)
+        for k in range(32):
+            m = _rotation(lane, k)
+            ok = (m < nj) & (lane < nj) & ((k < 31) | (lane < 32))
+            out.append(np.stack([64 * A + lane[ok], 64 * A + m[ok]], -1))
+        return np.concatenate(out)
+    assert typ == 1 and ni == 2      # diagonal item of tiles a = 2A, b = 2A + 1
+    a, phase = 2 * A, B
+    na, nb = min(64, n - 64 * a), min(64, n - 64 * (a + 1))
+    o1 = 32 if phase else 0
     for k in range(32):
-        m = (lane + k + 1) & 63
-        ok = (m < nj) & (lane < nj) & ((k < 31) | (lane < 32))
-        out.append(np.stack([64 * A + lane[ok], 64 * A + m[ok]], -1))
+        m0, m1 = _rotation(lane, k), _rotation(lane, k + o1)
+        own = (k < 31) | (lane < 32)
+        if phase == 0:               # triangles of a (sub-task 0) and b (sub-task 1)
+            ok0 = (m0 < na) & (lane < na) & own
+            out.append(np.stack([64 * a + lane[ok0], 64 * a + m0[ok0]], -1))
+            if nb > 0:
+                ok1 = (m1 < nb) & (lane < nb) & own
+                out.append(np.stack([64 * (a + 1) + lane[ok1], 64 * (a + 1) + m1[ok1]], -1))
+        else:                        # cross pairs a x b, steps k and k + 32
+            assert nb > 0
+            for m in (m0, m1):
+                ok = m < nb
+                out.append(np.stack([64 * a + lane[ok], 64 * (a + 1) + m[ok]], -1))
     return np.concatenate(out)
 
 
@@ -79,26 +104,32 @@ def test_every_pair_exactly_once(harness, ni):
 
 
 def test_item_counts_per_replica(harness):
-    """NI = 1: one triangle per tile and one block item per later tile;
-    NI > 1: one block item per tile from the block's first tile on."""
+    """NI = 1: one triangle per tile and one block item per later tile; NI = 2:
+    two diagonal items per two-tile block and one block item per later tile;
+    NI > 2: one block item per tile from the block's first tile on."""
     items = _items(harness, 1, [1024])
     assert (items[:, 1] == 2).sum() == 16 and (items[:, 1] == 0).sum() == 16 * 15 // 2
     items = _items(harness, 2, [1024])
-    assert (items[:, 1] == 0).all() and len(items) == sum(16 - 2 * ib for ib in range(8))
+    assert (items[:, 1] == 1).sum() == 16 and (items[:, 1] == 0).sum() == sum(16 - 2 * ib - 2 for ib in range(8))
+    items = _items(harness, 2, [64 * 15])           # last block has one tile: no cross phase
+    assert (items[:, 1] == 1).sum() == 15
+    items = _items(harness, 4, [1024])
+    assert (items[:, 1] == 0).all() and len(items) == sum(16 - 4 * ib for ib in range(4))
 
 
-@pytest.mark.parametrize("K", [32, 64])
-def test_rotating_accumulator_lands_on_lane_plus_k(K):
+@pytest.mark.parametrize("K,o", [(32, 0), (64, 0), (32, 32)])
+def test_rotating_accumulator_lands_on_lane_plus_k(K, o):
     """acc <- acc[lane + 1] + c with c the contribution of lane l to
-    j = (l + k + 1) mod 64: after K steps lane l holds the sum for
-    j = (l + K) mod 64, which is where the kernels flush it."""
-    rng = np.random.default_rng(K)
+    j = (l + k + o + 1) mod 64 (o: the rotation offset of a diagonal item's
+    second sub-task): after K steps lane l holds the sum for j = (l + K + o)
+    mod 64, which is where the kernels flush it."""
+    rng = np.random.default_rng(K + o)
     lane = np.arange(64)
     contrib = np.zeros(64)
     acc = np.zeros(64)
     for k in range(K):
         c = rng.normal(size=64)
-        j = (lane + k + 1) & 63
+        j = (lane + k + o + 1) & 63
         np.add.at(contrib, j, c)
         acc = np.roll(acc, -1) + c
-    assert np.allclose(acc, contrib[(lane + K) & 63], rtol=0, atol=1e-12)
+    assert np.allclose(acc, contrib[(lane + K + o) & 63], rtol=0, atol=1e-12)
