@@ -302,6 +302,10 @@ typedef struct {
  * redox attempt (entity = replica, sub = 0: word 0 picks the site, word 1 the
  * new state, words 2-3 the acceptance uniform), 4 = exchange (entity = global
  * lower grid point, step = attempt index).
+ * Consecutive steps with no exchange attempt between them share one kernel
+ * (the closing tether and half kick of step n with the opening stages of step
+ * n+1, same roundings); the state after the call, ke included, is that of the
+ * last step.
  * Flags: GBR_MD_INIT_FORCES, GBR_MD_GRAPH. */
 int md_step(gbr_ctx* ctx, gbr_md_state* state, const gbr_md_params* params,
             uint64_t seed, uint64_t step0, int32_t n_steps, int32_t flags,

@@ -56,11 +56,15 @@ __global__ __launch_bounds__(256) void k_coef(
     const float* __restrict__ q, const float* __restrict__ rho, const float* __restrict__ R,
     const float* __restrict__ dRdpsi, const int64_t* __restrict__ dEdR_fx, double ketau,
     double offset, double* __restrict__ dEdR, float* __restrict__ cc,
-    int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
+    int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint64_t* __restrict__ step,
+    uint32_t* __restrict__ err)
 {
     const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
     const int lane = threadIdx.x & 63;
+    // inside md_step: the step counter advances here, once per step (nothing in
+    // this kernel reads it; the next step's kernels and the exchange do)
+    if (step && t == 0 && lane == 0) step[0] = step[0] + 1;
     const int2 tl = tiles[t];
     const int a0 = atom_off[tl.x], n = atom_off[tl.x + 1] - a0;
     const int li = tl.y * 64 + lane;
@@ -162,11 +166,12 @@ hipError_t launch_born_finalize(const gbr_ctx* c, const float* rho, float* R, fl
 }
 
 hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const float* R,
-                       const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, hipStream_t s) {
+                       const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, uint64_t* step,
+                       hipStream_t s) {
     const GBConstH k = make_const(c->prm);
     hipLaunchKernelGGL(k_coef, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, q, rho, R, dRdpsi, c->dEdR_fx, k.ke_d * k.tau_d, c->prm.offset,
-                       c->dEdR, c->chain_c, energy_fx, dEdq_fx, c->err);
+                       c->dEdR, c->chain_c, energy_fx, dEdq_fx, step, c->err);
     return hipGetLastError();
 }
 

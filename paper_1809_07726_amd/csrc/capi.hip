@@ -116,8 +116,9 @@ int upload(void* dst, const void* src, size_t bytes) {
     return GBR_OK;
 }
 
-// One force evaluation inside md_step (the caller has cleared the accumulators).
-int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, hipStream_t s) {
+// One force evaluation inside md_step (the caller has cleared the accumulators);
+// advance: the evaluation belongs to a step, whose counter then advances.
+int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, bool advance, hipStream_t s) {
     hipError_t e;
     {
         Timed t(c, GBR_K_BORN_PAIR, s);
@@ -142,7 +143,8 @@ int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "energy pair");
     {
         Timed t(c, GBR_K_PER_ATOM, s);
-        e = launch_coef(c, a.st.q, a.pr.rho, a.st.R, a.st.dRdpsi, a.st.energy_fx, nullptr, s);
+        e = launch_coef(c, a.st.q, a.pr.rho, a.st.R, a.st.dRdpsi, a.st.energy_fx, nullptr,
+                        advance ? c->step : nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(e, "coef");
     {
@@ -153,22 +155,28 @@ int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, hipStream_t s) {
     return GBR_OK;
 }
 
-// The launches of one MD step (kind bit 0: MC attempts, bit 1: exchange attempt).
+// Step kinds: MC attempts, exchange attempt after the step, the step opens
+// with the fused kernel that also closes the previous step, the step is closed
+// by its own k_md_last (last step of the call, or an exchange follows).
+enum { STEP_MC = 1, STEP_EX = 2, STEP_MID = 4, STEP_LAST = 8 };
+
+// The launches of one MD step.
 int md_one_step(gbr_ctx* c, const MDArgs& a, int kind, hipStream_t s) {
     hipError_t e;
     {
         Timed t(c, GBR_K_PER_ATOM, s);
-        e = launch_md_first(c, a, s);
+        e = launch_md_first(c, a, (kind & STEP_MID) != 0, s);
     }
     if (e != hipSuccess) return hip_fail(e, "md first");
-    int rc = md_forces(c, a, (kind & 1) != 0, s);
+    int rc = md_forces(c, a, (kind & STEP_MC) != 0, true, s);
     if (rc) return rc;
+    if (!(kind & STEP_LAST)) return GBR_OK;       // the next step's kernel closes this one
     {
         Timed t(c, GBR_K_PER_ATOM, s);
         e = launch_md_last(c, a, 1, s);
     }
     if (e != hipSuccess) return hip_fail(e, "md last");
-    if (kind & 2) {
+    if (kind & STEP_EX) {
         Timed t(c, GBR_K_EXCHANGE, s);
         e = launch_exchange_inputs(c, a.st, a.pr, c->ex_nH, c->ex_ne, c->ex_eps, s);
         if (e == hipSuccess)
@@ -448,7 +456,7 @@ int gb_energy_forces(gbr_ctx* c, const float* xyz, const float* q, const float* 
     if (e != hipSuccess) return hip_fail(e, "energy pair");
     {
         Timed t(c, GBR_K_PER_ATOM, s);
-        e = launch_coef(c, q, rho, R, dRdpsi, energy_fx, gq ? dEdq_fx : nullptr, s);
+        e = launch_coef(c, q, rho, R, dRdpsi, energy_fx, gq ? dEdq_fx : nullptr, nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(e, "coef");
     {
@@ -558,17 +566,21 @@ int md_step(gbr_ctx* c, gbr_md_state* st, const gbr_md_params* pr, uint64_t seed
         if (e == hipSuccess) e = launch_zero_i64(c->dEdR_fx, c->n_atoms, s);
         if (e == hipSuccess) e = launch_zero_i64(c->ke_fx, c->n_rep, s);
         if (e != hipSuccess) return hip_fail(e, "zero");
-        if (int rc = md_forces(c, a, false, s)) return rc;
+        if (int rc = md_forces(c, a, false, false, s)) return rc;
         e = launch_md_last(c, a, 0, s);
         if (e != hipSuccess) return hip_fail(e, "md init");
     }
     const bool use_graph = (flags & GBR_MD_GRAPH) != 0 && c->timer.mask == 0;
     uint64_t key = use_graph ? hash_args(a) : 0;
+    bool prev_open = false;            // the previous step still needs its closing half
     for (int32_t k = 0; k < n_steps; ++k) {
         const uint64_t n = step0 + (uint64_t)k;
         int kind = 0;
-        if (pr->mc_every > 0 && (n + 1) % (uint64_t)pr->mc_every == 0) kind |= 1;
-        if (pr->ex_every > 0 && (n + 1) % (uint64_t)pr->ex_every == 0) kind |= 2;
+        if (pr->mc_every > 0 && (n + 1) % (uint64_t)pr->mc_every == 0) kind |= STEP_MC;
+        if (pr->ex_every > 0 && (n + 1) % (uint64_t)pr->ex_every == 0) kind |= STEP_EX | STEP_LAST;
+        if (k == n_steps - 1) kind |= STEP_LAST;
+        if (prev_open) kind |= STEP_MID;
+        prev_open = !(kind & STEP_LAST);
         if (!use_graph) {
             if (int rc = md_one_step(c, a, kind, s)) return rc;
             continue;

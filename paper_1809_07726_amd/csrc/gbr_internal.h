@@ -62,8 +62,8 @@ struct gbr_ctx {
     uint32_t* err = nullptr;         // device error word
     gbr::Timer timer;
     // captured per-step graphs (plain, MC, EX, MC+EX)
-    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint64_t graph_key[4] = {0, 0, 0, 0};
+    hipGraphExec_t graph[16] = {};   // md_step graphs by step kind (mc, ex, mid head, last tail)
+    uint64_t graph_key[16] = {};
     hipStream_t cap_stream = nullptr;
 };
 
@@ -91,7 +91,8 @@ hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_born_finalize(const gbr_ctx* c, const float* rho, float* R, float* dRdpsi,
                                 double* psi, hipStream_t s);
 hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const float* R,
-                       const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, hipStream_t s);
+                       const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, uint64_t* step,
+                       hipStream_t s);
 hipError_t launch_rho_finalize(const gbr_ctx* c, const float* rho, const float* R,
                                const float* dRdpsi, const double* psi, int64_t* dEdrho_fx,
                                hipStream_t s);
@@ -106,7 +107,7 @@ struct MDArgs {
     uint64_t seed;
 };
 hipError_t launch_set_step(const gbr_ctx* c, uint64_t step0, hipStream_t s);
-hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, hipStream_t s);
+hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, bool mid, hipStream_t s);
 hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s);
 hipError_t launch_ke_out(const gbr_ctx* c, double* ke, hipStream_t s);
 hipError_t launch_mc(const gbr_ctx* c, const MDArgs& a, hipStream_t s);

@@ -10,20 +10,29 @@ namespace {
 
 // ----------------------------------------------------------- step counter
 // step[0] = index n of the step being executed; one thread of the step's
-// k_md_last (a kernel that does not read it) advances it to n + 1.
+// k_coef (a kernel that does not read it, run once per step after the step's
+// Langevin half and its Monte Carlo attempts) advances it to n + 1.
 __global__ void k_set_step(uint64_t* step, uint64_t step0) { step[0] = step0; }
 
 // ------------------------------------------------------ B, A, O, A stages
 // v += dt/2 F/m;  x += dt/2 v;  v = c1 v + c2 sqrt(kT/m) xi;  x += dt/2 v.
 // Also clears the accumulators of the force evaluation that follows, after
 // handing the previous step's kinetic energy to ke (may be NULL).
+// MID: the kernel also closes the previous step (what k_md_last does, with
+// the same roundings): tether forces at the current positions and the final
+// half kick.  Used when nothing reads the previous step's end state (no
+// exchange attempt after it, not the last step of the call), so that step's
+// kinetic and tether energies are not formed; the kinetic-energy accumulator
+// then stays at zero.
+template <bool MID>
 __global__ __launch_bounds__(256) void k_md_first(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
     const uint64_t* __restrict__ step, uint64_t seed, double hdt, double c1, double c2,
     const float* __restrict__ mass, const double* __restrict__ T_vals,
     const int32_t* __restrict__ target_idx, float* __restrict__ xyz, float* __restrict__ v,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ psi_fx,
-    int64_t* __restrict__ dEdR_fx, int64_t* __restrict__ ke_fx, double* __restrict__ ke)
+    int64_t* __restrict__ dEdR_fx, int64_t* __restrict__ ke_fx, double* __restrict__ ke,
+    const float* __restrict__ x0, double k_t, uint32_t* __restrict__ err)
 {
     const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
@@ -33,7 +42,7 @@ __global__ __launch_bounds__(256) void k_md_first(
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
     const int li = tl.y * 64 + lane;
     if (tl.y == 0 && lane < 4) energy_fx[4 * rep + lane] = 0;
-    if (tl.y == 0 && lane == 0) {
+    if (!MID && tl.y == 0 && lane == 0) {
         if (ke) ke[rep] = from_fixed(ke_fx[rep], INV_FX_ENERGY);
         ke_fx[rep] = 0;
     }
@@ -50,7 +59,13 @@ __global__ __launch_bounds__(256) void k_md_first(
     for (int d = 0; d < 3; ++d) {
         const int64_t idx = (int64_t)d * ntot + a;
         double vv = v[idx], xx = xyz[idx];
-        vv += hdt * from_fixed(force_fx[idx], INV_FX_FORCE) * im;
+        int64_t f = force_fx[idx];
+        if (MID) {
+            const double dx = xx - (double)x0[idx];
+            f += to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
+            vv = (double)(float)(vv + hdt * from_fixed(f, INV_FX_FORCE) * im);
+        }
+        vv += hdt * from_fixed(f, INV_FX_FORCE) * im;
         xx += hdt * vv;
         vv = c1 * vv + c2 * sd * xi[d];
         xx += hdt * vv;
@@ -63,13 +78,13 @@ __global__ __launch_bounds__(256) void k_md_first(
 }
 
 // Tether k |x - x0|^2 added to the forces and the replica's energy slot 3;
-// then (kick) v += dt/2 F/m, the kinetic energy, and the step counter advances.
+// then (kick) v += dt/2 F/m and the kinetic energy.
 __global__ __launch_bounds__(256) void k_md_last(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
     int ntot, double hdt, double k_t, const float* __restrict__ mass,
     const float* __restrict__ x0, const float* __restrict__ xyz, float* __restrict__ v,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx,
-    uint64_t* __restrict__ step, int kick, uint32_t* __restrict__ err)
+    int kick, uint32_t* __restrict__ err)
 {
     const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
@@ -101,7 +116,6 @@ __global__ __launch_bounds__(256) void k_md_last(
     if (lane == 0) {
         atomic_add_fx(&energy_fx[4 * rep + 3], to_fixed(se, FX_ENERGY, err));
         atomic_add_fx(&ke_fx[rep], to_fixed(sk, FX_ENERGY, err));
-        if (kick && t == 0) step[0] = step[0] + 1;
     }
 }
 
@@ -434,14 +448,16 @@ hipError_t launch_set_step(const gbr_ctx* c, uint64_t step0, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, hipStream_t s) {
+hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, bool mid, hipStream_t s) {
     const double hdt = 0.5 * a.pr.dt;
     const double c1 = exp(-a.pr.gamma * a.pr.dt);
     const double c2 = sqrt(1.0 - c1 * c1);
-    hipLaunchKernelGGL(k_md_first, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
-                       c->atom_off, c->n_atoms, c->step, a.seed, hdt, c1, c2, a.pr.mass,
-                       a.pr.grid.T_vals, a.st.target_idx, a.st.xyz, a.st.v, a.st.force_fx,
-                       a.st.energy_fx, c->psi_fx, c->dEdR_fx, c->ke_fx, a.st.ke);
+#define GBR_MDF(MID) hipLaunchKernelGGL(k_md_first<MID>, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, \
+        c->n_tiles, c->atom_off, c->n_atoms, c->step, a.seed, hdt, c1, c2, a.pr.mass, a.pr.grid.T_vals, \
+        a.st.target_idx, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->psi_fx, c->dEdR_fx, \
+        c->ke_fx, a.st.ke, a.pr.x0, a.pr.k_tether, c->err)
+    if (mid) GBR_MDF(true); else GBR_MDF(false);
+#undef GBR_MDF
     return hipGetLastError();
 }
 
@@ -449,7 +465,7 @@ hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream
     hipLaunchKernelGGL(k_md_last, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.mass,
                        a.pr.x0, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx,
-                       c->step, kick, c->err);
+                       kick, c->err);
     return hipGetLastError();
 }
 
