@@ -26,6 +26,8 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+#include <cstddef>
 #include <vector>
 
 namespace gbr {
@@ -62,6 +64,19 @@ inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vec
             }
             for (int32_t j = j0; j < T; ++j) out.push_back(make_item(r, ITEM_BLOCK, ib, j));
         }
+    }
+    // Each eighth of the list goes to one XCD, whose wavefronts take it in
+    // order: within each eighth, the 64-step block items first and the 32-step
+    // triangle and diagonal items last, so that the end of the pass (when the
+    // CUs drain) runs the short items.
+    const size_t n = out.size(), parts = 8;
+    std::vector<PairItem> tmp;
+    for (size_t p = 0; p < parts; ++p) {
+        const size_t b = n * p / parts, e = n * (p + 1) / parts;
+        tmp.clear();
+        for (size_t i = b; i < e; ++i) if (((uint32_t)out[i].x >> 30) == (uint32_t)ITEM_BLOCK) tmp.push_back(out[i]);
+        for (size_t i = b; i < e; ++i) if (((uint32_t)out[i].x >> 30) != (uint32_t)ITEM_BLOCK) tmp.push_back(out[i]);
+        std::copy(tmp.begin(), tmp.end(), out.begin() + (ptrdiff_t)b);
     }
 }
 

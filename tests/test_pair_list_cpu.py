@@ -91,7 +91,13 @@ def _pairs_of_item(n, ni, typ, A, B):
 def test_every_pair_exactly_once(harness, ni):
     sizes = [1, 2, 63, 64, 65, 127, 128, 129, 200, 511, 640, 1000]
     items = _items(harness, ni, sizes)
-    assert np.all(np.diff(items[:, 0]) >= 0), "items grouped by replica"
+    # each eighth of the list (one XCD's share): 64-step block items first, then
+    # the 32-step triangle and diagonal items
+    N = len(items)
+    for p in range(8):
+        t = items[N * p // 8:N * (p + 1) // 8, 1]
+        short = t != 0
+        assert not np.any(short[:-1] & ~short[1:]), p
     for r, n in enumerate(sizes):
         its = items[items[:, 0] == r]
         P = np.concatenate([_pairs_of_item(n, ni, *it[1:]) for it in its]) if len(its) else np.zeros((0, 2), int)
