@@ -45,13 +45,16 @@ inline PairItem make_item(int32_t rep, int32_t type, int32_t a, int32_t b) {
     return PairItem{rep | (type << 30), (a << 16) | b};
 }
 
-// Items of every replica in order; within a replica, I block by I block.
+// Items of every replica, within a replica I block by I block; then each
+// eighth of the list reordered (below).
 inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vector<PairItem>& out) {
     out.clear();
+    std::vector<uint32_t> rank;                 // position of each item within its replica
     for (int32_t r = 0; r < n_rep; ++r) {
         const int32_t n = off[r + 1] - off[r];
         const int32_t T = (n + 63) / 64;
         const int32_t B = (n + 64 * ni - 1) / (64 * ni);
+        const size_t first = out.size();
         for (int32_t ib = 0; ib < B; ++ib) {
             int32_t j0 = ib * ni;                   // first J tile of the block items
             if (ni == 1) {
@@ -64,18 +67,33 @@ inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vec
             }
             for (int32_t j = j0; j < T; ++j) out.push_back(make_item(r, ITEM_BLOCK, ib, j));
         }
+        for (size_t i = first; i < out.size(); ++i) rank.push_back((uint32_t)(i - first));
     }
     // Each eighth of the list goes to one XCD, whose wavefronts take it in
-    // order: within each eighth, the 64-step block items first and the 32-step
+    // order.  Within each eighth: the 64-step block items first and the 32-step
     // triangle and diagonal items last, so that the end of the pass (when the
-    // CUs drain) runs the short items.
+    // CUs drain) runs the short items; and within each of the two groups the
+    // replicas interleaved (items ordered by their position within their
+    // replica, then by replica), so that wavefronts that run at the same time
+    // (consecutive items) work on different replicas and their atomic flushes
+    // go to different atoms.  The order changes no result: every item's
+    // arithmetic is the same wherever it sits, and fixed-point sums do not
+    // depend on order.
     const size_t n = out.size(), parts = 8;
+    std::vector<size_t> idx;
     std::vector<PairItem> tmp;
     for (size_t p = 0; p < parts; ++p) {
         const size_t b = n * p / parts, e = n * (p + 1) / parts;
+        idx.clear();
+        for (size_t i = b; i < e; ++i) idx.push_back(i);
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t u, size_t v) {
+            const bool su = ((uint32_t)out[u].x >> 30) != (uint32_t)ITEM_BLOCK;
+            const bool sv = ((uint32_t)out[v].x >> 30) != (uint32_t)ITEM_BLOCK;
+            if (su != sv) return sv;                    // block items first
+            return rank[u] < rank[v];                   // then by rank; ties keep replica order
+        });
         tmp.clear();
-        for (size_t i = b; i < e; ++i) if (((uint32_t)out[i].x >> 30) == (uint32_t)ITEM_BLOCK) tmp.push_back(out[i]);
-        for (size_t i = b; i < e; ++i) if (((uint32_t)out[i].x >> 30) != (uint32_t)ITEM_BLOCK) tmp.push_back(out[i]);
+        for (size_t i : idx) tmp.push_back(out[i]);
         std::copy(tmp.begin(), tmp.end(), out.begin() + (ptrdiff_t)b);
     }
 }

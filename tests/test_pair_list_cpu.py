@@ -2,7 +2,8 @@
 host code, compiled here with g++: with the kernels' masking rules (i < j in
 block items, the half last step of a triangle), every unordered pair of every
 replica is met exactly once, for every register blocking and for ragged
-replica sizes."""
+replica sizes; and the list order within each eighth (block items first,
+replicas interleaved) is the one the builder states."""
 import os
 import subprocess
 
@@ -41,6 +42,25 @@ def harness(tmp_path_factory):
 def _items(exe, ni, sizes):
     out = subprocess.check_output([exe, str(ni)] + [str(s) for s in sizes], text=True)
     return np.array([list(map(int, l.split())) for l in out.splitlines()], dtype=np.int64).reshape(-1, 4)
+
+
+def _natural_items(ni, n):
+    """(type, A, B) of one replica's items in their order within the replica:
+    I block by I block, its triangle or diagonal items, then its block items."""
+    T, B = (n + 63) // 64, (n + 64 * ni - 1) // (64 * ni)
+    out = []
+    for ib in range(B):
+        j0 = ib * ni
+        if ni == 1:
+            out.append((2, ib, ib))
+            j0 = ib + 1
+        elif ni == 2:
+            out.append((1, ib, 0))
+            if 2 * ib + 1 < T:
+                out.append((1, ib, 1))
+            j0 = 2 * ib + 2
+        out += [(0, ib, j) for j in range(j0, T)]
+    return out
 
 
 def _rotation(lane, k):
@@ -89,15 +109,22 @@ def _pairs_of_item(n, ni, typ, A, B):
 
 @pytest.mark.parametrize("ni", [1, 2, 4, 8])
 def test_every_pair_exactly_once(harness, ni):
-    sizes = [1, 2, 63, 64, 65, 127, 128, 129, 200, 511, 640, 1000]
+    sizes = [1, 2, 63, 64, 65, 127, 128, 129, 200, 511, 640, 1000, 3000]
     items = _items(harness, ni, sizes)
     # each eighth of the list (one XCD's share): 64-step block items first, then
-    # the 32-step triangle and diagonal items
+    # the 32-step triangle and diagonal items; within each group the replicas
+    # interleaved: items by their position within their replica, then replica
     N = len(items)
+    natural = [_natural_items(ni, n) for n in sizes]
+    assert sorted(map(tuple, items.tolist())) == sorted(
+        (r, *it) for r, its in enumerate(natural) for it in its)
+    rank = np.array([natural[r].index((t, a, b)) for r, t, a, b in items.tolist()])
     for p in range(8):
-        t = items[N * p // 8:N * (p + 1) // 8, 1]
-        short = t != 0
+        sl = slice(N * p // 8, N * (p + 1) // 8)
+        short = items[sl, 1] != 0
         assert not np.any(short[:-1] & ~short[1:]), p
+        key = short * 10**9 + rank[sl] * 10**3 + items[sl, 0]
+        assert np.all(np.diff(key) > 0), p
     for r, n in enumerate(sizes):
         its = items[items[:, 0] == r]
         P = np.concatenate([_pairs_of_item(n, ni, *it[1:]) for it in its]) if len(its) else np.zeros((0, 2), int)
