@@ -10,10 +10,11 @@
 // j = (l + k + 1) mod 64, read from LDS, and adds its contribution into a
 // per-lane accumulator that is first rotated by one lane (DPP wave_rol:1,
 // folded into the add).  The accumulator that lane l adds into in step k
-// therefore always belongs to the j it is working on; after K steps lane l
-// holds the accumulator of j = (l + K) mod 64 (K = 64 for blocks and squares,
-// 32 for triangles).  This replaces a 64-lane reduction per j with one DPP add
-// per component per step.
+// therefore always belongs to the j it is working on; an item that runs steps
+// k0 .. k1 - 1 (0 .. 63 for a block, 0 .. 31 or 32 .. 63 for half of one, 0 ..
+// 31 for a triangle) ends with lane l holding the accumulator of
+// j = (l + k1) mod 64.  This replaces a 64-lane reduction per j with one DPP
+// add per component per step.
 //
 // Contributions to i accumulate per lane in FP32.  At the end of the item
 // every per-atom partial is rounded to 64-bit fixed point and added with an
@@ -64,14 +65,15 @@ struct ItemGeom {
     bool tri;       // triangle item (NI = 1 only)
     bool diag;      // diagonal item of a two-tile block (NI = 2 only)
     int phase;      // diagonal item: 0 = both tiles' own pairs, 1 = the cross pairs
-    int ksteps;     // rotation steps of the item
+    int k0, k1;     // rotation steps k0 .. k1 - 1 of the item
 };
 
 template <int NI>
 __device__ __forceinline__ ItemGeom item_geom(const int2 wi, const int32_t* __restrict__ atom_off) {
     ItemGeom g;
-    g.rep = wi.x & 0x3FFFFFFF;
+    g.rep = wi.x & 0x3FFFFFF;
     const int type = (int)((unsigned)wi.x >> 30);
+    const int half = (wi.x >> 26) & 3;              // block items: 0 whole, 1 / 2 halves
     const int A = wi.y >> 16, B = wi.y & 0xFFFF;
     g.a0 = atom_off[g.rep];
     g.n = atom_off[g.rep + 1] - g.a0;
@@ -83,13 +85,15 @@ __device__ __forceinline__ ItemGeom item_geom(const int2 wi, const int32_t* __re
         g.jbase = g.phase ? g.ibase + 64 : g.ibase;     // tile of LDS slot 0
         g.nj = min(64, g.n - g.jbase);
         g.u_lim = g.ibase + 64 < g.n ? 2 : 1;           // tile b exists
-        g.ksteps = 32;
+        g.k0 = 0;
+        g.k1 = 32;
     } else {
         g.phase = 0;
         g.ibase = A * 64 * NI;
         g.jbase = B * 64;
         g.nj = min(64, g.n - g.jbase);
-        g.ksteps = g.tri ? 32 : 64;
+        g.k0 = half == 2 ? 32 : 0;
+        g.k1 = (g.tri || half == 1) ? 32 : 64;
         // I sub-blocks u with a valid pair: ibase + 64u < jbase + nj (and < n)
         const int span = g.jbase + g.nj - g.ibase;
         g.u_lim = min(NI, (span + 63) >> 6);
@@ -121,13 +125,13 @@ __device__ __forceinline__ bool pair_ok(const ItemGeom& g, int lane, int k, int 
 template <int NI, typename K>
 __device__ __forceinline__ void run_item(const ItemGeom& g, K& kloop) {
     if constexpr (NI == 1) {
-        int f1 = 0;
-        if (g.nj == 64) f1 = g.tri ? 31 : 64;
-        if (f1 > 0) kloop(std::true_type{}, 0, f1);
-        if (f1 < g.ksteps) kloop(std::false_type{}, f1, g.ksteps);
+        int f1 = g.k0;
+        if (g.nj == 64) f1 = g.tri ? 31 : g.k1;
+        if (f1 > g.k0) kloop(std::true_type{}, g.k0, f1);
+        if (f1 < g.k1) kloop(std::false_type{}, f1, g.k1);
     } else {
-        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{}, 0, 64);
-        else kloop(std::false_type{}, 0, 64);
+        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{}, g.k0, g.k1);
+        else kloop(std::false_type{}, g.k0, g.k1);
     }
 }
 
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
         for (int u = 0; u < NI; ++u)
             if (u < g.u_lim && li[u] < g.n)
                 atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed(acc[u], FX_FORCE, err));
-        const int jl = g.jbase + ((lane + g.ksteps) & 63);
+        const int jl = g.jbase + ((lane + g.k1) & 63);
         if (jl < g.n) atomic_add_fx(&psi_fx[g.a0 + jl], to_fixed(accj[0], FX_FORCE, err));
         if (NSL > 1 && g.diag && g.u_lim > 1) {
             const int jl1 = g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63);
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             atomic_add_fx(&dEdR_fx[a], to_fixed((double)aj.R * taup, FX_FORCE, err));
             if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)aj.q * sq_ke_in, FX_FORCE, err));
         };
-        flush_j(g.jbase + ((lane + g.ksteps) & 63), accj[0]);
+        flush_j(g.jbase + ((lane + g.k1) & 63), accj[0]);
         if (NSL > 1 && g.diag && g.u_lim > 1)
             flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
         const double sgb = wave_sum_d(-(double)taup * (double)e_g);
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
             atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(aj.z, FX_FORCE, err));
             if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(aj.r, FX_FORCE, err));
         };
-        flush_j(g.jbase + ((lane + g.ksteps) & 63), accj[0]);
+        flush_j(g.jbase + ((lane + g.k1) & 63), accj[0]);
         if (NSL > 1 && g.diag && g.u_lim > 1)
             flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
     }

@@ -21,7 +21,13 @@
 //                 triangles of a and of b, phase 1 = the cross pairs a x b,
 //                 rotation steps 0..31 and 32..63 side by side.  Phase 1 exists
 //                 only if tile b does.
-// Encoding: x = rep | (type << 30), y = (A << 16) | B (A = IB for blocks).
+// The last ceil(nb / SPLIT_DEN) block items of each replica's nb (in the order
+// below) run as two halves each: rotation steps 0..31 and 32..63, the j
+// accumulators of the first half ending on lane (l + 32) mod 64, those of the
+// second back on lane l.  The choice depends on the replica alone, so a
+// replica's results do not depend on the rest of the batch.
+// Encoding: x = rep | (half << 26) | (type << 30), half = 0 (whole), 1, 2;
+// y = (A << 16) | B (A = IB for blocks).
 #pragma once
 
 #include <stdint.h>
@@ -35,14 +41,15 @@ namespace gbr {
 enum : int32_t { ITEM_BLOCK = 0, ITEM_DIAG = 1, ITEM_TRIANGLE = 2 };
 
 constexpr int32_t MAX_TILES = 65535;          // per replica (16-bit tile fields)
-constexpr int32_t MAX_REPLICAS = 1 << 30;     // 30-bit replica field
+constexpr int32_t MAX_REPLICAS = 1 << 26;     // 26-bit replica field
+constexpr int32_t SPLIT_DEN = 16;
 
 struct PairItem {
     int32_t x, y;
 };
 
-inline PairItem make_item(int32_t rep, int32_t type, int32_t a, int32_t b) {
-    return PairItem{rep | (type << 30), (a << 16) | b};
+inline PairItem make_item(int32_t rep, int32_t type, int32_t a, int32_t b, int32_t half = 0) {
+    return PairItem{rep | (half << 26) | (type << 30), (a << 16) | b};
 }
 
 // Items of every replica, within a replica I block by I block; then each
@@ -50,35 +57,56 @@ inline PairItem make_item(int32_t rep, int32_t type, int32_t a, int32_t b) {
 inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vector<PairItem>& out) {
     out.clear();
     std::vector<uint32_t> rank;                 // position of each item within its replica
+    std::vector<PairItem> one;
     for (int32_t r = 0; r < n_rep; ++r) {
         const int32_t n = off[r + 1] - off[r];
         const int32_t T = (n + 63) / 64;
         const int32_t B = (n + 64 * ni - 1) / (64 * ni);
-        const size_t first = out.size();
+        one.clear();
         for (int32_t ib = 0; ib < B; ++ib) {
             int32_t j0 = ib * ni;                   // first J tile of the block items
             if (ni == 1) {
-                out.push_back(make_item(r, ITEM_TRIANGLE, ib, ib));
+                one.push_back(make_item(r, ITEM_TRIANGLE, ib, ib));
                 j0 = ib + 1;
             } else if (ni == 2) {
-                out.push_back(make_item(r, ITEM_DIAG, ib, 0));
-                if (2 * ib + 1 < T) out.push_back(make_item(r, ITEM_DIAG, ib, 1));
+                one.push_back(make_item(r, ITEM_DIAG, ib, 0));
+                if (2 * ib + 1 < T) one.push_back(make_item(r, ITEM_DIAG, ib, 1));
                 j0 = 2 * ib + 2;
             }
-            for (int32_t j = j0; j < T; ++j) out.push_back(make_item(r, ITEM_BLOCK, ib, j));
+            for (int32_t j = j0; j < T; ++j) one.push_back(make_item(r, ITEM_BLOCK, ib, j));
         }
-        for (size_t i = first; i < out.size(); ++i) rank.push_back((uint32_t)(i - first));
+        size_t nb = 0;
+        for (const PairItem& it : one) nb += ((uint32_t)it.x >> 30) == (uint32_t)ITEM_BLOCK;
+        size_t split = (nb + SPLIT_DEN - 1) / SPLIT_DEN;    // block items still to split, from the end
+        for (size_t k = one.size(); k-- > 0 && split > 0;) {
+            if (((uint32_t)one[k].x >> 30) != (uint32_t)ITEM_BLOCK) continue;
+            one[k].x |= 1 << 26;
+            --split;
+        }
+        for (size_t k = 0; k < one.size(); ++k) {
+            out.push_back(one[k]);
+            rank.push_back((uint32_t)k);
+            if (((one[k].x >> 26) & 3) == 1) {
+                out.push_back(PairItem{(one[k].x & ~(3 << 26)) | (2 << 26), one[k].y});
+                rank.push_back((uint32_t)k);
+            }
+        }
     }
     // Each eighth of the list goes to one XCD, whose wavefronts take it in
     // order.  Within each eighth: the 64-step block items first and the 32-step
-    // triangle and diagonal items last, so that the end of the pass (when the
-    // CUs drain) runs the short items; and within each of the two groups the
-    // replicas interleaved (items ordered by their position within their
-    // replica, then by replica), so that wavefronts that run at the same time
-    // (consecutive items) work on different replicas and their atomic flushes
-    // go to different atoms.  The order changes no result: every item's
-    // arithmetic is the same wherever it sits, and fixed-point sums do not
-    // depend on order.
+    // items last (triangle and diagonal items, then first halves, then second
+    // halves), so that the end of the pass (when the CUs drain) runs short
+    // items; and within each of these groups the replicas interleaved (items
+    // ordered by their position within their replica, then by replica), so
+    // that wavefronts that run at the same time (consecutive items) work on
+    // different replicas and their atomic flushes go to different atoms.  The
+    // order changes no result: every item's arithmetic is the same wherever it
+    // sits, and fixed-point sums do not depend on order.
+    auto group = [&](size_t i) -> int {
+        const int half = (out[i].x >> 26) & 3;
+        if (half) return 1 + half;
+        return ((uint32_t)out[i].x >> 30) != (uint32_t)ITEM_BLOCK ? 1 : 0;
+    };
     const size_t n = out.size(), parts = 8;
     std::vector<size_t> idx;
     std::vector<PairItem> tmp;
@@ -87,10 +115,9 @@ inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vec
         idx.clear();
         for (size_t i = b; i < e; ++i) idx.push_back(i);
         std::stable_sort(idx.begin(), idx.end(), [&](size_t u, size_t v) {
-            const bool su = ((uint32_t)out[u].x >> 30) != (uint32_t)ITEM_BLOCK;
-            const bool sv = ((uint32_t)out[v].x >> 30) != (uint32_t)ITEM_BLOCK;
-            if (su != sv) return sv;                    // block items first
-            return rank[u] < rank[v];                   // then by rank; ties keep replica order
+            const int gu = group(u), gv = group(v);
+            if (gu != gv) return gu < gv;
+            return rank[u] < rank[v];                   // ties keep replica order
         });
         tmp.clear();
         for (size_t i : idx) tmp.push_back(out[i]);

@@ -2,8 +2,10 @@
 host code, compiled here with g++: with the kernels' masking rules (i < j in
 block items, the half last step of a triangle), every unordered pair of every
 replica is met exactly once, for every register blocking and for ragged
-replica sizes; and the list order within each eighth (block items first,
-replicas interleaved) is the one the builder states."""
+replica sizes, with the last block items of each replica split into two
+halves (rotation steps 0..31 and 32..63); and the list order within each
+eighth (block items first, replicas interleaved) is the one the builder
+states."""
 import os
 import subprocess
 
@@ -24,7 +26,8 @@ int main(int argc, char** argv) {
     std::vector<gbr::PairItem> items;
     gbr::build_pair_items(off.data(), (int32_t)off.size() - 1, ni, items);
     for (const auto& it : items)
-        std::printf("%d %d %d %d\n", it.x & 0x3FFFFFFF, (int)((unsigned)it.x >> 30), it.y >> 16, it.y & 0xFFFF);
+        std::printf("%d %d %d %d %d\n", it.x & 0x3FFFFFF, (int)((unsigned)it.x >> 30), it.y >> 16,
+                    it.y & 0xFFFF, (it.x >> 26) & 3);
     return 0;
 }
 """
@@ -40,13 +43,18 @@ def harness(tmp_path_factory):
 
 
 def _items(exe, ni, sizes):
+    """Rows (replica, type, A, B, half)."""
     out = subprocess.check_output([exe, str(ni)] + [str(s) for s in sizes], text=True)
-    return np.array([list(map(int, l.split())) for l in out.splitlines()], dtype=np.int64).reshape(-1, 4)
+    return np.array([list(map(int, l.split())) for l in out.splitlines()], dtype=np.int64).reshape(-1, 5)
+
+
+SPLIT_DEN = 16      # the last ceil(nb / 16) block items of a replica run as halves
 
 
 def _natural_items(ni, n):
-    """(type, A, B) of one replica's items in their order within the replica:
-    I block by I block, its triangle or diagonal items, then its block items."""
+    """(type, A, B, half) of one replica's items in their order within the
+    replica: I block by I block, its triangle or diagonal items, then its block
+    items; the last ceil(nb / 16) block items as two halves each."""
     T, B = (n + 63) // 64, (n + 64 * ni - 1) // (64 * ni)
     out = []
     for ib in range(B):
@@ -60,24 +68,34 @@ def _natural_items(ni, n):
                 out.append((1, ib, 1))
             j0 = 2 * ib + 2
         out += [(0, ib, j) for j in range(j0, T)]
-    return out
+    blocks = [k for k, it in enumerate(out) if it[0] == 0]
+    split = set(blocks[len(blocks) - (len(blocks) + SPLIT_DEN - 1) // SPLIT_DEN:])
+    res = []
+    for k, it in enumerate(out):
+        res += [(*it, 1), (*it, 2)] if k in split else [(*it, 0)]
+    return res
 
 
 def _rotation(lane, k):
     return (lane + k + 1) & 63
 
 
-def _pairs_of_item(n, ni, typ, A, B):
-    """Pairs (i, j) the kernels evaluate for one item, following their masks."""
+def _pairs_of_item(n, ni, typ, A, B, half):
+    """Pairs (i, j) the kernels evaluate for one item, following their masks
+    and step ranges."""
     lane = np.arange(64)
     out = []
     if typ == 0:                     # block: i in block A (inside the replica) x tile B, i < j
         nj = min(64, n - 64 * B)
-        i = 64 * ni * A + np.arange(64 * ni)
-        i = i[i < n]
-        j = 64 * B + np.arange(nj)
-        P = np.stack(np.meshgrid(i, j, indexing="ij"), -1).reshape(-1, 2)
-        return P[P[:, 0] < P[:, 1]]
+        k0, k1 = {0: (0, 64), 1: (0, 32), 2: (32, 64)}[half]
+        for k in range(k0, k1):
+            m = _rotation(lane, k)
+            for u in range(ni):
+                i = 64 * ni * A + 64 * u + lane
+                ok = (m < nj) & (i < 64 * B + m) & (i < n)
+                out.append(np.stack([i[ok], 64 * B + m[ok]], -1))
+        return np.concatenate(out)
+    assert half == 0
     if typ == 2:                     # triangle (NI = 1): 32 rotation steps
         assert A == B and ni == 1
         nj = min(64, n - 64 * A)
@@ -118,12 +136,13 @@ def test_every_pair_exactly_once(harness, ni):
     natural = [_natural_items(ni, n) for n in sizes]
     assert sorted(map(tuple, items.tolist())) == sorted(
         (r, *it) for r, its in enumerate(natural) for it in its)
-    rank = np.array([natural[r].index((t, a, b)) for r, t, a, b in items.tolist()])
+    # rank: position of the (whole) item within its replica, halves sharing it
+    whole = [[it[:3] for k, it in enumerate(nat) if it[3] != 2] for nat in natural]
+    rank = np.array([whole[r].index((t, a, b)) for r, t, a, b, h in items.tolist()])
+    group = np.where(items[:, 4] > 0, 1 + items[:, 4], (items[:, 1] != 0).astype(np.int64))
     for p in range(8):
         sl = slice(N * p // 8, N * (p + 1) // 8)
-        short = items[sl, 1] != 0
-        assert not np.any(short[:-1] & ~short[1:]), p
-        key = short * 10**9 + rank[sl] * 10**3 + items[sl, 0]
+        key = group[sl] * 10**9 + rank[sl] * 10**3 + items[sl, 0]
         assert np.all(np.diff(key) > 0), p
     for r, n in enumerate(sizes):
         its = items[items[:, 0] == r]
@@ -140,22 +159,29 @@ def test_item_counts_per_replica(harness):
     """NI = 1: one triangle per tile and one block item per later tile; NI = 2:
     two diagonal items per two-tile block and one block item per later tile;
     NI > 2: one block item per tile from the block's first tile on."""
+    def blocks(items):              # block items, a split one counted once
+        return ((items[:, 1] == 0) & (items[:, 4] != 2)).sum()
+
     items = _items(harness, 1, [1024])
-    assert (items[:, 1] == 2).sum() == 16 and (items[:, 1] == 0).sum() == 16 * 15 // 2
+    assert (items[:, 1] == 2).sum() == 16 and blocks(items) == 16 * 15 // 2
+    assert (items[:, 4] == 1).sum() == (items[:, 4] == 2).sum() == 8        # ceil(120 / 16)
     items = _items(harness, 2, [1024])
-    assert (items[:, 1] == 1).sum() == 16 and (items[:, 1] == 0).sum() == sum(16 - 2 * ib - 2 for ib in range(8))
+    assert (items[:, 1] == 1).sum() == 16 and blocks(items) == sum(16 - 2 * ib - 2 for ib in range(8))
+    assert (items[:, 4] == 1).sum() == 4                                    # ceil(56 / 16)
     items = _items(harness, 2, [64 * 15])           # last block has one tile: no cross phase
     assert (items[:, 1] == 1).sum() == 15
     items = _items(harness, 4, [1024])
-    assert (items[:, 1] == 0).all() and len(items) == sum(16 - 4 * ib for ib in range(4))
+    assert (items[:, 1] == 0).all() and blocks(items) == sum(16 - 4 * ib for ib in range(4))
+    assert (items[:, 4] == 1).sum() == 3                                    # ceil(40 / 16)
 
 
 @pytest.mark.parametrize("K,o", [(32, 0), (64, 0), (32, 32)])
 def test_rotating_accumulator_lands_on_lane_plus_k(K, o):
     """acc <- acc[lane + 1] + c with c the contribution of lane l to
-    j = (l + k + o + 1) mod 64 (o: the rotation offset of a diagonal item's
-    second sub-task): after K steps lane l holds the sum for j = (l + K + o)
-    mod 64, which is where the kernels flush it."""
+    j = (l + k + o + 1) mod 64 (o: the first rotation step, 32 for a diagonal
+    item's second sub-task and for the second half of a block item): after K
+    steps lane l holds the sum for j = (l + K + o) mod 64, which is where the
+    kernels flush it."""
     rng = np.random.default_rng(K + o)
     lane = np.arange(64)
     contrib = np.zeros(64)
