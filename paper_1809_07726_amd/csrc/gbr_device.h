@@ -22,6 +22,8 @@ constexpr double FX_FORCE = 1099511627776.0;   // 2^40
 constexpr double FX_ENERGY = 4294967296.0;     // 2^32
 constexpr double INV_FX_FORCE = 1.0 / FX_FORCE;
 constexpr double INV_FX_ENERGY = 1.0 / FX_ENERGY;
+constexpr float FXF_FORCE = 1099511627776.0f;  // the same scales as floats
+constexpr float FXF_ENERGY = 4294967296.0f;
 
 enum Stream : uint32_t { STREAM_O = 1, STREAM_MCPH = 2, STREAM_MCRED = 3, STREAM_EX = 4 };
 
@@ -41,6 +43,26 @@ __device__ __forceinline__ long long to_fixed(double v, double scale, uint32_t* 
     return (long long)__builtin_rint(s);
 }
 
+// The same for an FP32 value and a power-of-two scale, in FP32 instructions
+// only: v * scale is exact, so is its rounding to an integer r (|r| < 2^62),
+// and |r| = hi 2^32 + lo with hi = floor(|r| 2^-32) and lo = |r| - hi 2^32 in
+// [0, 2^32) is split exactly (lo's bits are a subset of |r|'s); the sign is
+// applied to the 64-bit integer.  The result equals to_fixed((double)v, scale).
+__device__ __forceinline__ long long to_fixed_f(float v, float scale, uint32_t* err) {
+    const float s = v * scale;
+    if (!(fabsf(s) < 4.6116860184273879e18f)) {   // 2^62
+        raise_error(err, (v == v && fabsf(v) <= 3.4028234663852886e38f) ? GBR_ERR_OVERFLOW
+                                                                         : GBR_ERR_NONFINITE);
+        return 0;
+    }
+    const float r = __builtin_rintf(s);
+    const float a = fabsf(r);
+    const float hi = floorf(a * 2.3283064365386963e-10f);         // 2^-32
+    const float lo = __builtin_fmaf(hi, -4294967296.0f, a);
+    const unsigned long long u = ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+    return r < 0.0f ? -(long long)u : (long long)u;
+}
+
 __device__ __forceinline__ void atomic_add_fx(int64_t* p, long long v) {
     if (v != 0)
         __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(p),
@@ -57,6 +79,27 @@ __device__ __forceinline__ double from_fixed(int64_t v, double inv_scale) {
 // value: loads indexed by it (work items, replica offsets) become scalar loads.
 __device__ __forceinline__ int wave_in_group() {
     return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// Sum of a 64-bit integer over the wavefront, in lane 63 (other lanes hold
+// partial sums): an inclusive scan within each row of 16 lanes (DPP row_shr
+// 1, 2, 4, 8), then the row totals carried up (row_bcast 15, 31).  Integer
+// sums do not depend on order.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, true);
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ long long wave_sum_i64_lane63(long long x) {
+    unsigned long long v = (unsigned long long)x;
+    v += dpp_u64<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_u64<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_u64<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_u64<0x118, 0xF>(v);   // row_shr:8
+    v += dpp_u64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_u64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return (long long)v;
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {

@@ -267,12 +267,12 @@ __global__ __launch_bounds__(256) void k_born_pair(
 #pragma unroll
         for (int u = 0; u < NI; ++u)
             if (u < g.u_lim && li[u] < g.n)
-                atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed(acc[u], FX_FORCE, err));
+                atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed_f(acc[u], FXF_FORCE, err));
         const int jl = g.jbase + ((lane + g.k1) & 63);
-        if (jl < g.n) atomic_add_fx(&psi_fx[g.a0 + jl], to_fixed(accj[0], FX_FORCE, err));
+        if (jl < g.n) atomic_add_fx(&psi_fx[g.a0 + jl], to_fixed_f(accj[0], FXF_FORCE, err));
         if (NSL > 1 && g.diag && g.u_lim > 1) {
             const int jl1 = g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63);
-            if (jl1 < g.n) atomic_add_fx(&psi_fx[g.a0 + jl1], to_fixed(accj[NSL - 1], FX_FORCE, err));
+            if (jl1 < g.n) atomic_add_fx(&psi_fx[g.a0 + jl1], to_fixed_f(accj[NSL - 1], FXF_FORCE, err));
         }
     }
 }
@@ -429,32 +429,33 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         for (int u = 0; u < NI; ++u) {
             if (u < g.u_lim && li[u] < g.n) {
                 const int a = g.a0 + li[u];
-                atomic_add_fx(&force_fx[a], to_fixed(fxi[u], FX_FORCE, err));
-                atomic_add_fx(&force_fx[ntot + a], to_fixed(fyi[u], FX_FORCE, err));
-                atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzi[u], FX_FORCE, err));
-                atomic_add_fx(&dEdR_fx[a], to_fixed((double)dRi[u] * taup, FX_FORCE, err));
-                if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)dqi[u] * sq_ke_in, FX_FORCE, err));
+                atomic_add_fx(&force_fx[a], to_fixed_f(fxi[u], FXF_FORCE, err));
+                atomic_add_fx(&force_fx[ntot + a], to_fixed_f(fyi[u], FXF_FORCE, err));
+                atomic_add_fx(&force_fx[2 * ntot + a], to_fixed_f(fzi[u], FXF_FORCE, err));
+                atomic_add_fx(&dEdR_fx[a], to_fixed_f(dRi[u] * taup, FXF_FORCE, err));
+                if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed_f(dqi[u] * sq_ke_in, FXF_FORCE, err));
             }
         }
         auto flush_j = [&](int jl, const EnergyJ& aj) {
             if (jl >= g.n) return;
             const int a = g.a0 + jl;
-            atomic_add_fx(&force_fx[a], to_fixed(aj.x, FX_FORCE, err));
-            atomic_add_fx(&force_fx[ntot + a], to_fixed(aj.y, FX_FORCE, err));
-            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(aj.z, FX_FORCE, err));
-            atomic_add_fx(&dEdR_fx[a], to_fixed((double)aj.R * taup, FX_FORCE, err));
-            if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed((double)aj.q * sq_ke_in, FX_FORCE, err));
+            atomic_add_fx(&force_fx[a], to_fixed_f(aj.x, FXF_FORCE, err));
+            atomic_add_fx(&force_fx[ntot + a], to_fixed_f(aj.y, FXF_FORCE, err));
+            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed_f(aj.z, FXF_FORCE, err));
+            atomic_add_fx(&dEdR_fx[a], to_fixed_f(aj.R * taup, FXF_FORCE, err));
+            if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed_f(aj.q * sq_ke_in, FXF_FORCE, err));
         };
         flush_j(g.jbase + ((lane + g.k1) & 63), accj[0]);
         if (NSL > 1 && g.diag && g.u_lim > 1)
             flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
-        const double sgb = wave_sum_d(-(double)taup * (double)e_g);
-        const double sc = wave_sum_d((double)e_c);
-        const double slj = wave_sum_d((double)e_lj);
-        if (lane == 0) {
-            atomic_add_fx(&energy_fx[4 * g.rep + 0], to_fixed(sgb, FX_ENERGY, err));
-            atomic_add_fx(&energy_fx[4 * g.rep + 1], to_fixed(sc, FX_ENERGY, err));
-            atomic_add_fx(&energy_fx[4 * g.rep + 2], to_fixed(slj, FX_ENERGY, err));
+        // per-lane energies to fixed point, summed over the wavefront as integers
+        const long long sgb = wave_sum_i64_lane63(to_fixed_f(-taup * e_g, FXF_ENERGY, err));
+        const long long sc = wave_sum_i64_lane63(to_fixed_f(e_c, FXF_ENERGY, err));
+        const long long slj = wave_sum_i64_lane63(to_fixed_f(e_lj, FXF_ENERGY, err));
+        if (lane == 63) {
+            atomic_add_fx(&energy_fx[4 * g.rep + 0], sgb);
+            atomic_add_fx(&energy_fx[4 * g.rep + 1], sc);
+            atomic_add_fx(&energy_fx[4 * g.rep + 2], slj);
         }
     }
 }
@@ -597,19 +598,19 @@ __global__ __launch_bounds__(256) void k_chain_pair(
         for (int u = 0; u < NI; ++u) {
             if (u < g.u_lim && li[u] < g.n) {
                 const int a = g.a0 + li[u];
-                atomic_add_fx(&force_fx[a], to_fixed(fxi[u], FX_FORCE, err));
-                atomic_add_fx(&force_fx[ntot + a], to_fixed(fyi[u], FX_FORCE, err));
-                atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(fzi[u], FX_FORCE, err));
-                if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(dri[u], FX_FORCE, err));
+                atomic_add_fx(&force_fx[a], to_fixed_f(fxi[u], FXF_FORCE, err));
+                atomic_add_fx(&force_fx[ntot + a], to_fixed_f(fyi[u], FXF_FORCE, err));
+                atomic_add_fx(&force_fx[2 * ntot + a], to_fixed_f(fzi[u], FXF_FORCE, err));
+                if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed_f(dri[u], FXF_FORCE, err));
             }
         }
         auto flush_j = [&](int jl, const ChainJ& aj) {
             if (jl >= g.n) return;
             const int a = g.a0 + jl;
-            atomic_add_fx(&force_fx[a], to_fixed(aj.x, FX_FORCE, err));
-            atomic_add_fx(&force_fx[ntot + a], to_fixed(aj.y, FX_FORCE, err));
-            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed(aj.z, FX_FORCE, err));
-            if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed(aj.r, FX_FORCE, err));
+            atomic_add_fx(&force_fx[a], to_fixed_f(aj.x, FXF_FORCE, err));
+            atomic_add_fx(&force_fx[ntot + a], to_fixed_f(aj.y, FXF_FORCE, err));
+            atomic_add_fx(&force_fx[2 * ntot + a], to_fixed_f(aj.z, FXF_FORCE, err));
+            if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed_f(aj.r, FXF_FORCE, err));
         };
         flush_j(g.jbase + ((lane + g.k1) & 63), accj[0]);
         if (NSL > 1 && g.diag && g.u_lim > 1)
