@@ -1,6 +1,7 @@
 """Device code of the library compiled to gfx950 assembly (hipcc -S, no GPU
 needed): no scalar-memory writes of any kind, no packed FP32 arithmetic (the
-build disables it), and no register spills in the force-only pair kernels."""
+build disables it), no register spills in the force-only pair kernels, and no
+FP64 arithmetic in the pair kernels."""
 import os
 import re
 import subprocess
@@ -50,3 +51,9 @@ def test_force_only_pair_kernels_do_not_spill(asm):
         grad = "ELb1E" in name                  # dE/dq or dE/drho variants
         if not grad:
             assert int(scratch) == 0, name
+
+
+def test_pair_kernels_hold_no_fp64_arithmetic(asm):
+    """The pair passes are FP32 throughout: partials reach fixed point through
+    FP32 instructions and energies are summed over the wavefront as integers."""
+    assert not re.findall(r"^\s+v_\w+_f64\b", asm["pair_kernels.hip"], re.M)
