@@ -48,13 +48,17 @@ int dev_alloc(T** p, size_t n) {
     return GBR_OK;
 }
 
-// Timing: a pair of events around each timed launch when enabled.
+// Timing: a pair of events per timed launch when enabled.  ext: the launch
+// records them itself, from its own dispatch (the pair kernels, through
+// hipExtLaunchKernel: no marker packets between kernels); otherwise they are
+// recorded on the stream around the launch.
 struct Timed {
     gbr_ctx* c;
     int kind;
     hipStream_t s;
-    hipEvent_t stop = nullptr;
-    Timed(gbr_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
+    bool ext;
+    LaunchEvents ev;
+    Timed(gbr_ctx* c_, int kind_, hipStream_t s_, bool ext_ = false) : c(c_), kind(kind_), s(s_), ext(ext_) {
         Timer& t = c->timer;
         if (!(t.mask & (1 << kind_))) return;
         if (t.used + 2 > t.pool.size()) {
@@ -63,15 +67,16 @@ struct Timed {
             for (size_t i = old; i < t.pool.size(); ++i)
                 if (hipEventCreate(&t.pool[i]) != hipSuccess) t.pool[i] = nullptr;
         }
-        hipEvent_t start = t.pool[t.used];
-        stop = t.pool[t.used + 1];
-        if (!start || !stop) { stop = nullptr; return; }
+        hipEvent_t start = t.pool[t.used], stop = t.pool[t.used + 1];
+        if (!start || !stop) return;
         t.kind.push_back(kind);
         t.used += 2;
-        (void)hipEventRecord(start, s);
+        ev.start = start;
+        ev.stop = stop;
+        if (!ext) (void)hipEventRecord(start, s);
     }
     ~Timed() {
-        if (stop) (void)hipEventRecord(stop, s);
+        if (ev.stop && !ext) (void)hipEventRecord(ev.stop, s);
     }
 };
 
@@ -121,8 +126,8 @@ int upload(void* dst, const void* src, size_t bytes) {
 int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, bool advance, hipStream_t s) {
     hipError_t e;
     {
-        Timed t(c, GBR_K_BORN_PAIR, s);
-        e = launch_born_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, s);
+        Timed t(c, GBR_K_BORN_PAIR, s, true);
+        e = launch_born_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "born pair");
     {
@@ -136,9 +141,9 @@ int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, bool advance, hipStream
         if (e != hipSuccess) return hip_fail(e, "mc");
     }
     {
-        Timed t(c, GBR_K_ENERGY_PAIR, s);
+        Timed t(c, GBR_K_ENERGY_PAIR, s, true);
         e = launch_energy_pair(c, a.st.xyz, a.st.q, a.st.R, a.pr.sigma, a.pr.eps, a.st.force_fx,
-                               a.st.energy_fx, nullptr, s);
+                               a.st.energy_fx, nullptr, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "energy pair");
     {
@@ -148,8 +153,8 @@ int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, bool advance, hipStream
     }
     if (e != hipSuccess) return hip_fail(e, "coef");
     {
-        Timed t(c, GBR_K_CHAIN_PAIR, s);
-        e = launch_chain_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, a.st.force_fx, nullptr, s);
+        Timed t(c, GBR_K_CHAIN_PAIR, s, true);
+        e = launch_chain_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, a.st.force_fx, nullptr, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "chain pair");
     return GBR_OK;
@@ -414,8 +419,8 @@ int gb_born_radii(gbr_ctx* c, const float* xyz, const float* rho, const float* s
     hipError_t e = launch_zero_i64(c->psi_fx, c->n_atoms, s);
     if (e != hipSuccess) return hip_fail(e, "zero");
     {
-        Timed t(c, GBR_K_BORN_PAIR, s);
-        e = launch_born_pair(c, xyz, rho, screen, s);
+        Timed t(c, GBR_K_BORN_PAIR, s, true);
+        e = launch_born_pair(c, xyz, rho, screen, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "born pair");
     {
@@ -450,8 +455,8 @@ int gb_energy_forces(gbr_ctx* c, const float* xyz, const float* q, const float* 
     if (e == hipSuccess) e = launch_zero_i64(c->dEdR_fx, N, s);
     if (e != hipSuccess) return hip_fail(e, "zero");
     {
-        Timed t(c, GBR_K_ENERGY_PAIR, s);
-        e = launch_energy_pair(c, xyz, q, R, sigma, eps, force_fx, energy_fx, gq ? dEdq_fx : nullptr, s);
+        Timed t(c, GBR_K_ENERGY_PAIR, s, true);
+        e = launch_energy_pair(c, xyz, q, R, sigma, eps, force_fx, energy_fx, gq ? dEdq_fx : nullptr, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "energy pair");
     {
@@ -460,8 +465,8 @@ int gb_energy_forces(gbr_ctx* c, const float* xyz, const float* q, const float* 
     }
     if (e != hipSuccess) return hip_fail(e, "coef");
     {
-        Timed t(c, GBR_K_CHAIN_PAIR, s);
-        e = launch_chain_pair(c, xyz, rho, screen, force_fx, gr ? dEdrho_fx : nullptr, s);
+        Timed t(c, GBR_K_CHAIN_PAIR, s, true);
+        e = launch_chain_pair(c, xyz, rho, screen, force_fx, gr ? dEdrho_fx : nullptr, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "chain pair");
     if (gr) {

@@ -76,15 +76,20 @@ struct GBConstH {
 GBConstH make_const(const gbr_gb_params& p);
 
 // kernel launchers (pair kernels) ----------------------------------------
+// ev: timing events (start, stop) recorded by the kernel's own dispatch
+// (hipExtLaunchKernel), or null.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
 hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho,
-                            const float* screen, hipStream_t s);
+                            const float* screen, hipStream_t s, LaunchEvents ev = {});
 hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q,
                               const float* R, const float* sigma, const float* eps,
                               int64_t* force_fx, int64_t* energy_fx, int64_t* dEdq_fx,
-                              hipStream_t s);
+                              hipStream_t s, LaunchEvents ev = {});
 hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rho,
                              const float* screen, int64_t* force_fx, int64_t* dEdrho_fx,
-                             hipStream_t s);
+                             hipStream_t s, LaunchEvents ev = {});
 
 // per-atom kernels ------------------------------------------------------------
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);

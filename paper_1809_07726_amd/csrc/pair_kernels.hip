@@ -29,6 +29,8 @@
 // eight XCDs) walk a contiguous range of the item list, i.e. of replicas.
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "gbr_device.h"
 #include "gbr_internal.h"
 #include "pair_list.h"
@@ -627,6 +629,13 @@ int grid_for(const gbr_ctx* c, int n_items) {
     return (g + 7) & ~7;   // multiple of 8 for the XCD remapping
 }
 
+// Nothing to launch: the timing events still get recorded (an empty interval).
+hipError_t no_launch(hipStream_t s, const LaunchEvents& ev) {
+    if (ev.start) (void)hipEventRecord(ev.start, s);
+    if (ev.stop) (void)hipEventRecord(ev.stop, s);
+    return hipSuccess;
+}
+
 const PairList& list_for(const gbr_ctx* c, int ni) {
     switch (ni) {
         case 1: return c->lists[0];
@@ -641,13 +650,13 @@ const PairList& list_for(const gbr_ctx* c, int ni) {
 namespace gbr {
 
 hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho,
-                            const float* screen, hipStream_t s)
+                            const float* screen, hipStream_t s, LaunchEvents ev)
 {
     const PairList& L = list_for(c, c->ni_born);
-    if (L.n_items == 0) return hipSuccess;
+    if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
     const float off = (float)c->prm.offset;
-#define GBR_BORN(NI) hipLaunchKernelGGL(k_born_pair<NI>, grid, block, 0, s, L.items, L.n_items, \
+#define GBR_BORN(NI) hipExtLaunchKernelGGL(k_born_pair<NI>, grid, block, 0, s, ev.start, ev.stop, 0, L.items, L.n_items, \
         c->atom_off, c->n_atoms, xyz, rho, screen, off, c->psi_fx, c->err)
     switch (L.ni) {
         case 1: GBR_BORN(1); break;
@@ -662,14 +671,14 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
 hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q,
                               const float* R, const float* sigma, const float* eps,
                               int64_t* force_fx, int64_t* energy_fx, int64_t* dEdq_fx,
-                              hipStream_t s)
+                              hipStream_t s, LaunchEvents ev)
 {
     const PairList& L = list_for(c, c->ni_energy);
-    if (L.n_items == 0) return hipSuccess;
+    if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
     const float sq = (float)sqrt(c->prm.k_e / c->prm.eps_in);
     const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
-#define GBR_EN(NI, GQ) hipLaunchKernelGGL((k_energy_pair<NI, GQ>), grid, block, 0, s, L.items, \
+#define GBR_EN(NI, GQ) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ>), grid, block, 0, s, ev.start, ev.stop, 0, L.items, \
         L.n_items, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, force_fx, \
         c->dEdR_fx, energy_fx, dEdq_fx, c->err)
     const bool gq = dEdq_fx != nullptr;
@@ -685,13 +694,13 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
 
 hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rho,
                              const float* screen, int64_t* force_fx, int64_t* dEdrho_fx,
-                             hipStream_t s)
+                             hipStream_t s, LaunchEvents ev)
 {
     const PairList& L = list_for(c, c->ni_chain);
-    if (L.n_items == 0) return hipSuccess;
+    if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
     const float off = (float)c->prm.offset;
-#define GBR_CH(NI, RH) hipLaunchKernelGGL((k_chain_pair<NI, RH>), grid, block, 0, s, L.items, \
+#define GBR_CH(NI, RH) hipExtLaunchKernelGGL((k_chain_pair<NI, RH>), grid, block, 0, s, ev.start, ev.stop, 0, L.items, \
         L.n_items, c->atom_off, c->n_atoms, xyz, rho, screen, c->chain_c, off, force_fx, \
         dEdrho_fx, c->err)
     const bool rh = dEdrho_fx != nullptr;
