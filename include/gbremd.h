@@ -172,10 +172,12 @@ int gbr_set_launch(gbr_ctx* ctx, int32_t waves_per_group, int32_t groups_per_cu)
  * chosen from the largest replica at context creation. */
 int gbr_set_blocking(gbr_ctx* ctx, int32_t ni_born, int32_t ni_energy, int32_t ni_chain);
 
-/* Kernel timing with HIP events recorded on the launch stream around every
- * kernel of the GBR_K_* kinds whose bit (1 << kind) is set in kinds_mask
- * (0 disables; eager launches only: md_step does not replay graphs while any
- * kind is timed). */
+/* Kernel timing with HIP events for every kernel of the GBR_K_* kinds whose
+ * bit (1 << kind) is set in kinds_mask (0 disables; eager launches only:
+ * md_step does not replay graphs while any kind is timed).  The pair kernels'
+ * events come from their own dispatch (hipExtLaunchKernel) and time the kernel
+ * alone; the other kinds' events are recorded on the launch stream around the
+ * launch. */
 int gbr_set_timing(gbr_ctx* ctx, int32_t kinds_mask);
 /* Synchronizes; ms_out[k] = summed milliseconds, count_out[k] = launches, for
  * k < GBR_K_COUNT; then resets the accumulators. */
