@@ -94,6 +94,21 @@ def test_full_size_e_ph_t_batch_sampled():
     _any_size_properties(b, g)
 
 
+def test_full_size_e_ph_t_batch_in_the_tuned_launch():
+    """The benchmarked batch in the launch configuration bench.py times: the
+    autotuner's choice of register blocking and launch shape."""
+    from paper_1809_07726_amd.gb import Context
+    from paper_1809_07726_amd.tune import autotune
+    b = synth.make_config(2, per_replica_jitter=True)
+    ctx = Context(b["atom_off"])
+    tuned = autotune(ctx, to_dev(b).t, reps=3)
+    ctx.close()
+    print("tuned launch:", tuned["shape"], tuned["blocking"], flush=True)
+    g = gpu_eval(b, blocking=tuple(tuned["blocking"]), launch=tuple(tuned["shape"]))
+    _sample_check(b, g, [7, 130])
+    _any_size_properties(b, g)
+
+
 def test_full_size_e_ph_batch_sampled():
     b = synth.make_config(1, per_replica_jitter=True)
     g = gpu_eval(b)
