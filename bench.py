@@ -84,16 +84,19 @@ def traffic_from_profile(kernel, launches_bytes_alg):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(b, n_rep_sample, min_s=10.0, budget_s=20.0):
+def cpu_baseline(b, n_rep_sample, gpu_ref=None, min_s=10.0, budget_s=20.0):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
     full E+F gradient evaluations of successive replicas (cycling through the
     batch) until at least min_s seconds of CPU work, stopping at budget_s or
-    after n_rep_sample evaluations (0: no count limit)."""
+    after n_rep_sample evaluations (0: no count limit).  With gpu_ref = (E, F),
+    the GPU's energies [n_rep, 5] and forces [N, 3] at the same inputs, also
+    returns the GPU's error against FP64 on the replicas evaluated."""
     import oracle
     off = b["atom_off"]
     t0 = time.perf_counter()
     pairs = 0
     done = 0
+    first = {}
     while True:
         el = time.perf_counter() - t0
         if el > budget_s or (n_rep_sample and done >= n_rep_sample) or (el >= min_s and done >= 1):
@@ -101,17 +104,34 @@ def cpu_baseline(b, n_rep_sample, min_s=10.0, budget_s=20.0):
         r = done % b["n_rep"]
         done += 1
         a, c = off[r], off[r + 1]
-        oracle.gradient(b["xyz"][a:c], b["q"][a:c], b["rho"][a:c], b["screen"][a:c],
-                        b["sigma"][a:c], b["eps"][a:c])
+        E, gx, _, _ = oracle.gradient(b["xyz"][a:c], b["q"][a:c], b["rho"][a:c], b["screen"][a:c],
+                                      b["sigma"][a:c], b["eps"][a:c])
+        if r not in first:
+            first[r] = (E, gx)
         n = c - a
         pairs += n * (n - 1) // 2
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} replica evaluations ({done / b['n_rep']:.1f} passes over the "
-                      f"{b['n_rep']} replicas x {off[1] - off[0]} atoms): one FP64 Born-radii + energy + "
-                      f"analytic-gradient evaluation each ({dt:.1f} s)"}
+    sizes = np.diff(off)
+    size_txt = (f"{sizes[0]} atoms" if np.all(sizes == sizes[0]) else f"{sizes.min()}..{sizes.max()} atoms")
+    out = {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+           "sample": f"{done} replica evaluations ({done / b['n_rep']:.2f} passes over the "
+                     f"{b['n_rep']} replicas of {size_txt}): one FP64 Born-radii + energy + "
+                     f"analytic-gradient evaluation each ({dt:.1f} s)"}
+    err = None
+    if gpu_ref is not None and first:
+        Eg, Fg = gpu_ref
+        e_rel, gb_rel, f_rms = [], [], []
+        for r, (E, gx) in first.items():
+            a, c = off[r], off[r + 1]
+            e_rel.append(abs(Eg[r, 4] - E.sum()) / abs(E.sum()))
+            gb_rel.append(abs(Eg[r, 0] - E[0]) / abs(E[0]))
+            f_rms.append(float(np.sqrt(((Fg[a:c] + gx) ** 2).sum() / (gx ** 2).sum())))
+        err = {"replicas": len(first), "state": "the synthetic starting coordinates",
+               "energy_rel_max": max(e_rel), "e_gb_rel_max": max(gb_rel),
+               "force_rms_rel_max": max(f_rms)}
+    return out, err
 
 
 def _progress(msg):
@@ -142,6 +162,14 @@ def main():
     _progress(f"{w.name}: {b['n_rep']} replicas, {n_pairs} pairs per step; autotuning")
     tuned = autotune(ctx, dev.t)
     _progress(f"tuned {tuned}; warmup")
+    # the GPU's energies and forces at the starting coordinates: the cpu_baseline
+    # leg compares them with the FP64 oracle on the replicas it evaluates
+    t = dev.t
+    R0, dR0, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"], want_psi=False)
+    f0, e0, _, _ = ctx.energy_forces(t["xyz"], t["q"], t["rho"], t["screen"], t["sigma"], t["eps"], R0, dR0)
+    gpu_ref = (ctx.energies(e0).cpu().numpy(),
+               (f0.cpu().numpy() * 2.0 ** -40).reshape(3, -1).T.copy())
+    ctx.check()
     md.run(0, init_forces=True)
     md.run(args.warmup if not args.profile_only else 3, graph=args.graph)
     torch.cuda.synchronize()
@@ -180,9 +208,10 @@ def main():
     if cnt:
         avg = ms / cnt
         ach = flops[dom] * n_pairs / (avg * 1e-3) / 1e12
+        traffic = traffic_from_profile(dom, None)
         roofline = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
-                    "traffic": traffic_from_profile(dom, None),
+                    "traffic": traffic, "hbm_gbs": (traffic / (avg * 1e-3) / 1e9 if traffic else None),
                     "avg_launch_ms": avg, "launches": cnt,
                     "flop_per_pair": flops[dom], "pairs_per_launch": n_pairs}
     # the three pair passes side by side, from a short run after the timed region
@@ -268,10 +297,10 @@ def main():
     if "plain_eval_ms" in evals:
         evals["plain_eval_pairs_per_s"] = n_pairs / (evals["plain_eval_ms"] * 1e-3)
 
-    cpu = None
+    cpu, err64 = None, None
     if not args.no_cpu_baseline:
         _progress("oracle CPU baseline")
-        cpu = cpu_baseline(b, args.cpu_sample_replicas)
+        cpu, err64 = cpu_baseline(b, args.cpu_sample_replicas, gpu_ref)
 
     sizes = np.diff(b["atom_off"]).astype(int)
     atoms_per_replica = (int(sizes[0]) if np.all(sizes == sizes[0]) else
@@ -291,6 +320,7 @@ def main():
                              "i_atoms_per_lane_born_energy_chain": tuned["blocking"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "error_vs_fp64": err64,
         "pair_kernels": per_kernel,
         "graph_ms_per_step": graph_ms,
         "pair_kernels_note": f"all three passes timed with events over {n_break} steps after the timed region",
