@@ -168,23 +168,27 @@ def assemble(systems: list, reps_per_system: int, E_vals, pH_vals, T_vals, dim_o
     out = {k: cat(k) for k in ("xyz", "x0", "q", "rho", "screen", "sigma", "eps", "mass")}
     out["atom_off"] = atom_off
     out["n_rep"] = len(reps)
-    # sites
+    # sites: a site dict gives one charge column and one (nH, ne) entry per
+    # state; the tables are padded to the batch's largest state count
+    ms = max([2] + [len(s["nH"]) for rd in reps for s in rd["sites"]])
     site_off, site_atoms, site_type, n_states, state_q = [0], [], [], [], []
     state_nH, state_ne, ref_value, rep_site_off, site_rep = [], [], [], [0], []
     for r, rd in enumerate(reps):
         for s in rd["sites"]:
+            k = len(s["nH"])
+            qs = np.asarray(s["q_states"], np.float64).reshape(len(s["atoms"]), k)
             site_atoms.extend((s["atoms"] + atom_off[r]).tolist())
             site_off.append(len(site_atoms))
             site_type.append(s["type"])
-            n_states.append(2)
-            state_q.append(s["q_states"])
-            state_nH.extend(s["nH"])
-            state_ne.extend(s["ne"])
+            n_states.append(k)
+            state_q.append(np.pad(qs, ((0, 0), (0, ms - k))))
+            state_nH.extend(list(s["nH"]) + [0] * (ms - k))
+            state_ne.extend(list(s["ne"]) + [0] * (ms - k))
             ref_value.append(s["ref"])
             site_rep.append(r)
         rep_site_off.append(len(site_type))
     out.update({
-        "n_sites": len(site_type), "max_states": 2,
+        "n_sites": len(site_type), "max_states": ms,
         "site_off": np.asarray(site_off, np.int32), "site_atoms": np.asarray(site_atoms, np.int32),
         "site_type": np.asarray(site_type, np.int32), "n_states": np.asarray(n_states, np.int32),
         "state_q": (np.concatenate(state_q).reshape(-1) if state_q else np.zeros(0)).astype(np.float64),
@@ -192,7 +196,7 @@ def assemble(systems: list, reps_per_system: int, E_vals, pH_vals, T_vals, dim_o
         "ref_value": np.asarray(ref_value, np.float64),
         "rep_site_off": np.asarray(rep_site_off, np.int32), "site_rep": np.asarray(site_rep, np.int32),
         "site_state": np.zeros(len(site_type), np.int32),
-        "G_ref": np.zeros(2 * len(site_type), np.float64),   # filled by the consumer
+        "G_ref": np.zeros(ms * len(site_type), np.float64),  # filled by the consumer
     })
     # grid
     n_inst = len(systems) if per_replica is None else len(reps) // reps_per_system

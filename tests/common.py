@@ -8,21 +8,49 @@ from paper_1809_07726_amd import synth
 
 
 def oracle_reference_energies(batch, gb=None):
-    """G_ref per (site, state): 0 for state 0 and, for state 1, the change of
-    the electrostatic energy of the site's atoms alone (the reference compound)
-    at the batch's starting geometry.  An isolated site then titrates exactly
-    at pKa_ref / E0_ref."""
-    out = np.zeros(2 * batch["n_sites"])
+    """G_ref per (site, state): 0 for state 0 and, for every other state, the
+    change of the electrostatic energy of the site's atoms alone (the
+    reference compound) at the batch's starting geometry.  An isolated site
+    then titrates exactly at pKa_ref / E0_ref."""
     ms = batch["max_states"]
+    out = np.zeros(ms * batch["n_sites"])
     for s in range(batch["n_sites"]):
         a, b = batch["site_off"][s], batch["site_off"][s + 1]
         idx = batch["site_atoms"][a:b]
         xyz = batch["xyz"][idx].astype(np.float64)
         _, R, _ = oracle.born(xyz, batch["rho"][idx], batch["screen"][idx], gb)
-        q0 = batch["state_q"][a * ms:b * ms].reshape(-1, ms)[:, 0]
-        q1 = batch["state_q"][a * ms:b * ms].reshape(-1, ms)[:, 1]
-        out[s * ms + 1] = oracle.elec_energy(xyz, q1, R, gb) - oracle.elec_energy(xyz, q0, R, gb)
+        qs = batch["state_q"][a * ms:b * ms].reshape(-1, ms)
+        e0 = oracle.elec_energy(xyz, qs[:, 0], R, gb)
+        for k in range(1, int(batch["n_states"][s])):
+            out[s * ms + k] = oracle.elec_energy(xyz, qs[:, k], R, gb) - e0
     return out
+
+
+def with_diprotic_ph_sites(batch):
+    """The batch with every pH site given a third state that carries a second
+    proton (the state-1 charge increment added once more, N_H = 2): the
+    three-state site tables, padded to max_states = 3."""
+    b = dict(batch)
+    ms0, ns = batch["max_states"], batch["n_sites"]
+    assert ms0 == 2
+    ms = 3
+    q_old = np.asarray(batch["state_q"]).reshape(-1, ms0)
+    q = np.zeros((q_old.shape[0], ms))
+    q[:, :2] = q_old
+    nH = np.zeros(ns * ms, np.int32)
+    ne = np.zeros(ns * ms, np.int32)
+    n_states = np.asarray(batch["n_states"]).copy()
+    for s in range(ns):
+        a, c = batch["site_off"][s], batch["site_off"][s + 1]
+        nH[s * ms:s * ms + 2] = batch["state_nH"][s * ms0:s * ms0 + 2]
+        ne[s * ms:s * ms + 2] = batch["state_ne"][s * ms0:s * ms0 + 2]
+        if batch["site_type"][s] == synth.PH_SITE:
+            q[a:c, 2] = 2 * q_old[a:c, 1] - q_old[a:c, 0]
+            nH[s * ms + 2] = 2
+            n_states[s] = 3
+    b.update({"max_states": ms, "state_q": q.reshape(-1), "state_nH": nH, "state_ne": ne,
+              "n_states": n_states.astype(np.int32), "G_ref": np.zeros(ns * ms)})
+    return b
 
 
 def with_oracle_gref(batch, gb=None):
@@ -96,3 +124,34 @@ def four_state_constants(eps, T, pKa, E0):
             "pKa_red": pKa - (eps[1, 1] - eps[0, 1]) / (kT * c["ln10"]),
             "E0_deprot": E0 - (eps[0, 1] - eps[0, 0]) / c["F"],
             "E0_prot": E0 - (eps[1, 1] - eps[1, 0]) / c["F"]}
+
+
+def diprotic_site_batch(pH, seed=31, reps=1):
+    """One isolated pH site (its atoms only, from a 64-atom lattice system),
+    frozen (dt = 0), attempts every step, with a third state holding a second
+    proton (N_H = 0, 1, 2); reps independent copies, one replica each.  G_ref
+    is left for the caller."""
+    b = synth.make_config(0, n_atoms=64, seed=seed)
+    a, c = b["site_off"][0], b["site_off"][1]
+    idx = b["site_atoms"][a:c]
+    q2 = b["state_q"].reshape(-1, 2)[a:c]
+    sysd = {k: b[k][idx] for k in ("xyz", "x0", "q", "rho", "screen", "sigma", "eps", "mass")}
+    sysd["sites"] = [{"type": synth.PH_SITE, "atoms": np.arange(c - a),
+                      "q_states": np.stack([q2[:, 0], q2[:, 1], 2 * q2[:, 1] - q2[:, 0]], axis=1),
+                      "nH": [0, 1, 2], "ne": [0, 0, 0], "ref": b["ref_value"][0]}]
+    return synth.assemble([sysd] * reps, 1, (-0.2,), (pH,), (300.0,), (0,), dt=0.0, mc_every=1)
+
+
+def three_state_expected(d):
+    """Occupancies of N_H = 0, 1, 2 for an isolated site at pH - pKa_ref = d:
+    the attempts sample exp(-G/kT) with G(s) = kT ln10 (pH - pKa) N_H(s)."""
+    w = np.array([1.0, 10.0 ** -d, 10.0 ** (-2 * d)])
+    return w / w.sum()
+
+
+def batch_mean_bound(samples, n_batches=20):
+    """Five standard errors of the mean from batch means (robust to the
+    chain's correlation), plus one sample's weight."""
+    x = np.asarray(samples, np.float64)
+    m = x[: x.size // n_batches * n_batches].reshape(n_batches, -1).mean(1)
+    return 5.0 * m.std(ddof=1) / np.sqrt(n_batches) + 1.0 / x.size

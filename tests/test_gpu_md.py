@@ -9,7 +9,8 @@ import pytest
 import torch
 
 import oracle
-from common import with_oracle_gref
+from common import (batch_mean_bound, diprotic_site_batch, three_state_expected, with_diprotic_ph_sites,
+                    with_oracle_gref)
 from gpu_common import FX_E, soa_to_aos
 from paper_1809_07726_amd import synth
 
@@ -188,3 +189,43 @@ def test_gpu_titration_statistics(kind, delta):
     sigma = math.sqrt(f * (1 - f) / (n * reps) * (1 + lam) / max(1 - lam, 1e-12))
     assert abs(f_hat - f) <= 4 * sigma + 1.0 / (n * reps), (f_hat, f, sigma)
     ctx.close()
+
+
+def test_md_step_with_three_state_sites_matches_oracle():
+    """c0 with its pH site given a third (doubly protonated) state and attempts
+    every step: 25 steps follow the oracle's states exactly."""
+    b = with_oracle_gref(with_diprotic_ph_sites(synth.make_config(0)))
+    b["mc_every"] = 1
+    seed = 2100
+    g = _gpu_md(b, seed, [10, 15])
+    o = _oracle_md(b, seed, [10, 15])
+    for gs, os_ in zip(g, o):
+        assert np.array_equal(gs["site_state"], os_["site_state"])
+        assert np.allclose(gs["q"], os_["q"], atol=1e-6)
+        assert np.abs(gs["xyz"] - os_["xyz"].reshape(-1, 3)).max() < 2e-4
+    assert g[-1]["mc_stats"][0::2].sum() == o[-1]["mc_att"].sum() == 2 * 25
+
+
+@pytest.mark.parametrize("d", [-0.5, 0.0, 0.5])
+def test_gpu_three_state_site_statistics(d):
+    """64 frozen copies of an isolated three-state pH site (N_H = 0, 1, 2),
+    attempts every step on the GPU: the occupancies follow
+    p(s) proportional to 10^(-(pH - pKa) N_H(s))."""
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch, reference_energies
+    b = diprotic_site_batch(synth.PKA_REF + d, reps=64)
+    b["G_ref"] = reference_energies(b)          # the HIP path's own reference compound
+    ctx = Context(b["atom_off"])
+    dv = DeviceBatch.from_numpy(b)
+    md = MD(ctx, dv, b, seed=950 + int(100 * d))
+    md.run(1, init_forces=True)
+    n = 300
+    occ = np.zeros((n, 64), np.int64)
+    for k in range(n):
+        md.run(1)
+        occ[k] = dv.t["site_state"].cpu().numpy()
+    ctx.check()
+    ctx.close()
+    p = three_state_expected(d)
+    for s in range(3):
+        per_rep = (occ == s).mean(0)            # 64 independent chains
+        assert abs(per_rep.mean() - p[s]) <= batch_mean_bound(per_rep, 16), (s, per_rep.mean(), p[s])

@@ -122,3 +122,37 @@ def test_titration_delta_e_matches_oracle():
         ref = oracle.delta_e(x, b["q"][a0:a1], Ro, idx, qn)
         scale = abs(oracle.elec_energy(x, b["q"][a0:a1], Ro)) / len(idx)
         assert abs(dE[s] - ref) <= 1e-6 * max(abs(ref), scale), (s, dE[s], ref)
+
+
+def test_titration_delta_e_for_every_state_of_three_state_sites():
+    """pH sites with a third state: the candidate (site, state) energy change
+    for states 1 and 2 of every pH site (and state 1 of every redox site)
+    against the oracle's direct difference."""
+    from paper_1809_07726_amd.gb import Context
+    from gpu_common import to_dev
+    from common import with_diprotic_ph_sites
+    import torch
+    b = with_diprotic_ph_sites(synth.make_config(1, n_rep=3, per_replica_jitter=True))
+    d = to_dev(b)
+    ctx = Context(b["atom_off"])
+    t = d.t
+    R, _, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"])
+    pairs = [(s, k) for s in range(b["n_sites"]) for k in range(1, int(b["n_states"][s]))]
+    assert any(k == 2 for _, k in pairs)
+    cand = np.array(pairs, np.int32).reshape(-1)
+    dE = ctx.titration_delta_e(t["xyz"], t["q"], R, d, torch.as_tensor(cand)).cpu().numpy()
+    ctx.check()
+    ctx.close()
+    off = b["atom_off"]
+    ms = b["max_states"]
+    for i, (s, k) in enumerate(pairs):
+        r = int(np.searchsorted(off, b["site_atoms"][b["site_off"][s]], side="right") - 1)
+        a0, a1 = off[r], off[r + 1]
+        x = b["xyz"][a0:a1]
+        _, Ro, _ = oracle.born(x, b["rho"][a0:a1], b["screen"][a0:a1])
+        sl = slice(b["site_off"][s], b["site_off"][s + 1])
+        idx = b["site_atoms"][sl] - a0
+        qn = b["state_q"].reshape(-1, ms)[sl, k]
+        ref = oracle.delta_e(x, b["q"][a0:a1], Ro, idx, qn)
+        scale = abs(oracle.elec_energy(x, b["q"][a0:a1], Ro)) / len(idx)
+        assert abs(dE[i] - ref) <= 1e-6 * max(abs(ref), scale), (s, k, dE[i], ref)

@@ -12,7 +12,8 @@ from scipy.integrate import quad
 from scipy.optimize import brentq
 
 import oracle
-from common import oracle_reference_energies, with_oracle_gref
+from common import (batch_mean_bound, diprotic_site_batch, oracle_reference_energies, three_state_expected,
+                    with_oracle_gref)
 from paper_1809_07726_amd import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -325,6 +326,25 @@ def test_mc_reduced_fraction_is_nernst(d):
     f = 1.0 / (1.0 + math.exp(x))
     up, down = min(1.0, math.exp(-x)), min(1.0, math.exp(x))
     assert abs(f_hat - f) <= 4 * _two_state_sigma(f, up, down, n) + 1.0 / n
+
+
+@pytest.mark.parametrize("d", [-1.0, -0.5, 0.0, 0.5, 1.0])
+def test_mc_three_state_site_samples_boltzmann(d):
+    """A site with more than two states: the state is proposed uniformly among
+    the other states (a symmetric proposal), so the attempts sample
+    p(s) proportional to 10^(-(pH - pKa) N_H(s)) over N_H = 0, 1, 2."""
+    b = with_oracle_gref(diprotic_site_batch(synth.PKA_REF + d))
+    cfg, st, arr, keep = oracle.make_md(b, seed=300 + int(10 * d))
+    oracle.md_run(cfg, st, 0, 1, True)
+    n = 20000
+    states = np.empty(n, np.int64)
+    for k in range(n):
+        oracle.md_run(cfg, st, k + 1, 1, False)
+        states[k] = arr["site_state"][0]
+    p = three_state_expected(d)
+    for s in range(3):
+        hit = (states == s).astype(np.float64)
+        assert abs(hit.mean() - p[s]) <= batch_mean_bound(hit), (s, hit.mean(), p[s])
 
 
 # --------------------------- P11: coupled sites reproduce eqs. 6, 7 and 8
