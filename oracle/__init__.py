@@ -50,13 +50,16 @@ def lib():
 class GBParams(C.Structure):
     _fields_ = [("k_e", C.c_double), ("eps_in", C.c_double), ("eps_out", C.c_double),
                 ("offset", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
-                ("gamma", C.c_double)]
+                ("gamma", C.c_double), ("kappa", C.c_double), ("cut", C.c_double),
+                ("rgbmax", C.c_double)]
 
 
 def obc2(k_e=332.0522173, eps_in=1.0, eps_out=78.5, offset=0.09,
-         alpha=1.0, beta=0.8, gamma=4.85) -> GBParams:
-    """OBC-II parameter set (igb=2)."""
-    return GBParams(k_e, eps_in, eps_out, offset, alpha, beta, gamma)
+         alpha=1.0, beta=0.8, gamma=4.85, kappa=0.0, cut=0.0, rgbmax=0.0) -> GBParams:
+    """OBC-II parameter set (igb=2); kappa (1/A) screens the GB term with salt,
+    cut and rgbmax (A) truncate the pair energies and the descreening sum (0:
+    no salt, no cutoff)."""
+    return GBParams(k_e, eps_in, eps_out, offset, alpha, beta, gamma, kappa, cut, rgbmax)
 
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")

@@ -49,6 +49,9 @@ typedef struct {
     double eps_out;  /* solvent dielectric                                */
     double offset;   /* dielectric offset delta: rho~ = rho - delta (A)   */
     double alpha, beta, gamma;  /* OBC rescaling coefficients             */
+    double kappa;    /* Debye-Hueckel screening parameter (1/A), 0: no salt */
+    double cut;      /* pair energy cutoff (A), 0: none                     */
+    double rgbmax;   /* descreening cutoff (A), 0: none                     */
 } orc_gb;
 
 /* ===================================================== Philox4x32-10 (SC'11) */
@@ -185,7 +188,27 @@ static double orc_dist(const double* xyz, int i, int j, double d[3])
     return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
 }
 
-static double orc_tau(const orc_gb* p) { return 1.0 / p->eps_in - 1.0 / p->eps_out; }
+/* GB screening function: a GB pair term is -k_e q_i q_j g(f_ij) and a self
+ * term -(1/2) k_e q_i^2 g(R_i), with g(f) = (1/eps_in - exp(-kappa f)/eps_out)/f
+ * (the solvent's dielectric response screened by salt; kappa = 0 gives tau/f,
+ * tau = 1/eps_in - 1/eps_out). */
+static double orc_g(const orc_gb* p, double f)
+{
+    return (1.0 / p->eps_in - exp(-p->kappa * f) / p->eps_out) / f;
+}
+
+/* dg/df */
+static double orc_dg(const orc_gb* p, double f)
+{
+    double es = exp(-p->kappa * f);
+    return -(1.0 / p->eps_in - es / p->eps_out) / (f * f) + p->kappa * es / (p->eps_out * f);
+}
+
+/* Pair cutoffs: a pair at distance r takes part in the pair energies (Coulomb,
+ * GB, LJ) when r < cut, and in the descreening sum when r < rgbmax; a cutoff
+ * of 0 means none.  Self terms are always present. */
+static int orc_in_cut(const orc_gb* p, double r) { return p->cut <= 0.0 || r < p->cut; }
+static int orc_in_rgb(const orc_gb* p, double r) { return p->rgbmax <= 0.0 || r < p->rgbmax; }
 
 /* ====================================================== effective Born radii */
 /* psi_i = rho~_i * (1/2) sum_{j != i} h(r_ij; rho~_i, S_j rho~_j);
@@ -202,6 +225,7 @@ void orc_born(int n, const double* xyz, const double* rho, const double* scr,
             if (j == i) continue;
             double d[3];
             double r = orc_dist(xyz, i, j, d);
+            if (!orc_in_rgb(p, r)) continue;
             double sj = scr[j] * (rho[j] - p->offset);
             sum += orc_hct(r, rti, sj);
         }
@@ -226,21 +250,22 @@ static double orc_fgb(double r, double Ri, double Rj)
 }
 
 /* E[0] = E_GB (pairs i<j and the self terms), E[1] = E_Coulomb, E[2] = E_LJ,
- * all pairs, no exclusions, no cutoff; Lorentz-Berthelot LJ combination. */
+ * all pairs within the cutoff, no exclusions; Lorentz-Berthelot LJ
+ * combination. */
 void orc_energy(int n, const double* xyz, const double* q, const double* R,
                 const double* sig, const double* eps, const orc_gb* p, double E[3])
 {
-    double tau = orc_tau(p);
     double* row = (double*)calloc((size_t)3 * n, sizeof(double));
     #pragma omp parallel for schedule(dynamic, 8)
     for (int i = 0; i < n; ++i) {
-        double egb = -0.5 * p->k_e * tau * q[i] * q[i] / R[i];
+        double egb = -0.5 * p->k_e * q[i] * q[i] * orc_g(p, R[i]);
         double ec = 0.0, elj = 0.0;
         for (int j = i + 1; j < n; ++j) {
             double d[3];
             double r = orc_dist(xyz, i, j, d);
+            if (!orc_in_cut(p, r)) continue;
             double f = orc_fgb(r, R[i], R[j]);
-            egb += -p->k_e * tau * q[i] * q[j] / f;
+            egb += -p->k_e * q[i] * q[j] * orc_g(p, f);
             ec  += p->k_e / p->eps_in * q[i] * q[j] / r;
             double sij = 0.5 * (sig[i] + sig[j]);
             double eij = sqrt(eps[i] * eps[j]);
@@ -258,16 +283,16 @@ void orc_energy(int n, const double* xyz, const double* q, const double* R,
  * attempt changes). */
 double orc_elec_energy(int n, const double* xyz, const double* q, const double* R, const orc_gb* p)
 {
-    double tau = orc_tau(p);
     double* row = (double*)calloc((size_t)n, sizeof(double));
     #pragma omp parallel for schedule(dynamic, 8)
     for (int i = 0; i < n; ++i) {
-        double e = -0.5 * p->k_e * tau * q[i] * q[i] / R[i];
+        double e = -0.5 * p->k_e * q[i] * q[i] * orc_g(p, R[i]);
         for (int j = i + 1; j < n; ++j) {
             double d[3];
             double r = orc_dist(xyz, i, j, d);
+            if (!orc_in_cut(p, r)) continue;
             double f = orc_fgb(r, R[i], R[j]);
-            e += -p->k_e * tau * q[i] * q[j] / f + p->k_e / p->eps_in * q[i] * q[j] / r;
+            e += -p->k_e * q[i] * q[j] * orc_g(p, f) + p->k_e / p->eps_in * q[i] * q[j] / r;
         }
         row[i] = e;
     }
@@ -278,15 +303,16 @@ double orc_elec_energy(int n, const double* xyz, const double* q, const double* 
 }
 
 /* The symmetric electrostatic kernel: E_elec = (1/2) q^T K q with
- * K_ij = k_e (1/(eps_in r) - tau/f_ij) for i != j and K_ii = -k_e tau / R_i. */
+ * K_ij = k_e (1/(eps_in r) - g(f_ij)) for i != j within the cutoff (0 beyond)
+ * and K_ii = -k_e g(R_i). */
 static double orc_K(int n, const double* xyz, const double* R, const orc_gb* p, int i, int j)
 {
     (void)n;
-    double tau = orc_tau(p);
-    if (i == j) return -p->k_e * tau / R[i];
+    if (i == j) return -p->k_e * orc_g(p, R[i]);
     double d[3];
     double r = orc_dist(xyz, i, j, d);
-    return p->k_e * (1.0 / (p->eps_in * r) - tau / orc_fgb(r, R[i], R[j]));
+    if (!orc_in_cut(p, r)) return 0.0;
+    return p->k_e * (1.0 / (p->eps_in * r) - orc_g(p, orc_fgb(r, R[i], R[j])));
 }
 
 /* Titration energy change, plain definition: E_elec(q') - E_elec(q) with q'
@@ -337,7 +363,6 @@ void orc_gradient(int n, const double* xyz, const double* q, const double* rho, 
                   const double* sig, const double* eps, const orc_gb* p,
                   double E[3], double* dEdx, double* dEdq, double* dEdrho)
 {
-    double tau = orc_tau(p);
     double* psi = (double*)malloc((size_t)n * sizeof(double));
     double* R = (double*)malloc((size_t)n * sizeof(double));
     double* dRdpsi = (double*)malloc((size_t)n * sizeof(double));
@@ -349,16 +374,17 @@ void orc_gradient(int n, const double* xyz, const double* q, const double* rho, 
     /* dE/dR_i: self term plus every GB pair containing i. */
     #pragma omp parallel for schedule(dynamic, 8)
     for (int i = 0; i < n; ++i) {
-        double g = 0.5 * p->k_e * tau * q[i] * q[i] / (R[i] * R[i]);
+        double g = -0.5 * p->k_e * q[i] * q[i] * orc_dg(p, R[i]);
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
             double d[3];
             double r = orc_dist(xyz, i, j, d);
+            if (!orc_in_cut(p, r)) continue;
             double RR = R[i] * R[j];
             double D = r * r / (4.0 * RR);
             double f = orc_fgb(r, R[i], R[j]);
             double dfdRi = R[j] * exp(-D) * (1.0 + D) / (2.0 * f);
-            g += p->k_e * tau * q[i] * q[j] / (f * f) * dfdRi;
+            g += -p->k_e * q[i] * q[j] * orc_dg(p, f) * dfdRi;
         }
         dEdR[i] = g;
         c[i] = g * dRdpsi[i] * 0.5 * (rho[i] - p->offset);
@@ -368,7 +394,7 @@ void orc_gradient(int n, const double* xyz, const double* q, const double* rho, 
     for (int i = 0; i < n; ++i) {
         double rti = rho[i] - p->offset;
         double si = scr[i] * rti;
-        double gx = 0.0, gy = 0.0, gz = 0.0, gq = -p->k_e * tau * q[i] / R[i];
+        double gx = 0.0, gy = 0.0, gz = 0.0, gq = -p->k_e * q[i] * orc_g(p, R[i]);
         double sum_h = 0.0, sum_hrt = 0.0, sum_hs = 0.0;
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
@@ -376,28 +402,33 @@ void orc_gradient(int n, const double* xyz, const double* q, const double* rho, 
             double r = orc_dist(xyz, i, j, d);
             double rtj = rho[j] - p->offset;
             double sj = scr[j] * rtj;
-            double RR = R[i] * R[j];
-            double D = r * r / (4.0 * RR);
-            double f = orc_fgb(r, R[i], R[j]);
-            double dfdr = r / f * (1.0 - 0.25 * exp(-D));
-            /* pair energy derivative with respect to r at fixed Born radii */
-            double dgb = p->k_e * tau * q[i] * q[j] / (f * f) * dfdr;
-            double dc = -p->k_e / p->eps_in * q[i] * q[j] / (r * r);
-            double sij = 0.5 * (sig[i] + sig[j]);
-            double eij = sqrt(eps[i] * eps[j]);
-            double sr6 = pow(sij / r, 6.0);
-            double dlj = 4.0 * eij * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r;
-            /* Born-radius chain terms through psi_i and psi_j */
-            double hij_r, hij_rt, hij_s, hji_r, hji_rt, hji_s;
-            orc_hct_grad(r, rti, sj, &hij_r, &hij_rt, &hij_s);
-            orc_hct_grad(r, rtj, si, &hji_r, &hji_rt, &hji_s);
-            double dchain = c[i] * hij_r + c[j] * hji_r;
+            double dgb = 0.0, dc = 0.0, dlj = 0.0, dchain = 0.0;
+            if (orc_in_cut(p, r)) {
+                double RR = R[i] * R[j];
+                double D = r * r / (4.0 * RR);
+                double f = orc_fgb(r, R[i], R[j]);
+                double dfdr = r / f * (1.0 - 0.25 * exp(-D));
+                /* pair energy derivative with respect to r at fixed Born radii */
+                dgb = -p->k_e * q[i] * q[j] * orc_dg(p, f) * dfdr;
+                dc = -p->k_e / p->eps_in * q[i] * q[j] / (r * r);
+                double sij = 0.5 * (sig[i] + sig[j]);
+                double eij = sqrt(eps[i] * eps[j]);
+                double sr6 = pow(sij / r, 6.0);
+                dlj = 4.0 * eij * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r;
+                gq += (p->k_e * (1.0 / (p->eps_in * r) - orc_g(p, f))) * q[j];
+            }
+            if (orc_in_rgb(p, r)) {
+                /* Born-radius chain terms through psi_i and psi_j */
+                double hij_r, hij_rt, hij_s, hji_r, hji_rt, hji_s;
+                orc_hct_grad(r, rti, sj, &hij_r, &hij_rt, &hij_s);
+                orc_hct_grad(r, rtj, si, &hji_r, &hji_rt, &hji_s);
+                dchain = c[i] * hij_r + c[j] * hji_r;
+                sum_h += orc_hct(r, rti, sj);
+                sum_hrt += hij_rt;
+                sum_hs += c[j] * hji_s;
+            }
             double g = (dgb + dc + dlj + dchain) / r;
             gx += g * d[0]; gy += g * d[1]; gz += g * d[2];
-            gq += (p->k_e * (1.0 / (p->eps_in * r) - tau / f)) * q[j];
-            sum_h += orc_hct(r, rti, sj);
-            sum_hrt += hij_rt;
-            sum_hs += c[j] * hji_s;
         }
         if (dEdx) { dEdx[3 * i] = gx; dEdx[3 * i + 1] = gy; dEdx[3 * i + 2] = gz; }
         if (dEdq) dEdq[i] = gq;

@@ -269,6 +269,135 @@ def test_incremental_delta_e_equals_full_difference():
         assert abs(d_plain) > 1e-3
 
 
+# ------------------- P12: salt screening and pair cutoffs (the f3 extension)
+SALT = oracle.obc2(kappa=0.125)
+
+
+def test_salt_isolated_ion_born_energy():
+    """One ion in salt solution: E_GB = -(k_e q^2 / 2R)(1/eps_in - exp(-kappa R)/eps_out)
+    with R = rho~ (no descreening partner)."""
+    rho, q = 1.73, -0.61
+    xyz = np.zeros((1, 3))
+    _, R, _ = oracle.born(xyz, [rho], [0.8], SALT)
+    E = oracle.energy_at_R(xyz, [q], R, [3.0], [0.1], SALT)
+    rt = rho - 0.09
+    ref = -0.5 * KE * q * q / rt * (1.0 / SALT.eps_in - math.exp(-SALT.kappa * rt) / SALT.eps_out)
+    assert E[0] == pytest.approx(ref, rel=1e-14)
+
+
+def test_salt_two_ions_reach_the_debye_hueckel_interaction():
+    """Far apart (f -> r), the pair part of E_C + E_GB is the Debye-Hueckel
+    screened Coulomb interaction k_e q1 q2 exp(-kappa r) / (eps_out r); it is
+    isolated from the self terms by the charge bilinearity (E(q1, q2) -
+    E(q1, 0) - E(0, q2))."""
+    rho, scr = np.array([1.5, 1.7]), np.array([0.8, 0.8])
+    q1, q2 = 0.7, -0.4
+    for kappa in (0.0, 0.05, 0.3):
+        gb = oracle.obc2(kappa=kappa)
+        for r in (25.0, 40.0):          # beyond ~40 A the screened term cancels to roundoff
+            xyz = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+            _, R, _ = oracle.born(xyz, rho, scr, gb)
+            e = lambda a, b: oracle.elec_energy(xyz, np.array([a, b]), R, gb)
+            pair = e(q1, q2) - e(q1, 0.0) - e(0.0, q2)
+            target = KE * q1 * q2 * math.exp(-kappa * r) / (gb.eps_out * r)
+            # the pair term is a difference of terms larger by eps_out exp(kappa r) / eps_in:
+            # FP64 roundoff grows by that factor
+            tol = 1e-14 * gb.eps_out * math.exp(kappa * r) / gb.eps_in
+            assert pair == pytest.approx(target, rel=tol), (kappa, r)
+
+
+def _two_groups(sep=30.0, seed=5):
+    rng = np.random.default_rng(seed)
+    g1 = rng.uniform(0.0, 4.0, size=(5, 3))
+    g2 = rng.uniform(0.0, 4.0, size=(6, 3)) + np.array([sep, 0.0, 0.0])
+    n = 11
+    return (np.vstack([g1, g2]), rng.normal(0.0, 0.5, n), rng.uniform(1.2, 2.0, n),
+            rng.uniform(0.7, 0.9, n), rng.uniform(2.5, 3.5, n), rng.uniform(0.05, 0.2, n))
+
+
+def test_cutoffs_decouple_groups_farther_apart_than_the_cutoffs():
+    """Two compact groups 30 A apart with cut = 12 A and rgbmax = 15 A: the
+    truncated energies and gradients are those of each group alone without any
+    cutoff (every pair inside a group is within both cutoffs), with and without
+    salt.  A cutoff applied to a self term, a pair type left untruncated, or a
+    chain term kept across the descreening cutoff breaks this."""
+    x, q, rho, scr, sig, eps = _two_groups()
+    for kappa in (0.0, 0.2):
+        cut = oracle.obc2(kappa=kappa, cut=12.0, rgbmax=15.0)
+        none = oracle.obc2(kappa=kappa)
+        E, gx, gq, gr = oracle.gradient(x, q, rho, scr, sig, eps, cut)
+        parts = [oracle.gradient(x[sl], q[sl], rho[sl], scr[sl], sig[sl], eps[sl], none)
+                 for sl in (slice(0, 5), slice(5, 11))]
+        assert np.allclose(E, parts[0][0] + parts[1][0], rtol=1e-13, atol=0)
+        assert np.allclose(gx, np.vstack([parts[0][1], parts[1][1]]), rtol=1e-12, atol=1e-14)
+        assert np.allclose(gq, np.concatenate([parts[0][2], parts[1][2]]), rtol=1e-12, atol=1e-14)
+        assert np.allclose(gr, np.concatenate([parts[0][3], parts[1][3]]), rtol=1e-12, atol=1e-14)
+        # and the cutoffs do cut: without them the groups interact
+        E_all = oracle.gradient(x, q, rho, scr, sig, eps, none)[0]
+        assert abs(E_all[1] - E[1]) > 1e-6
+
+
+def test_cutoffs_beyond_every_pair_change_nothing():
+    b = _c0_small(64, seed=14)
+    args = (b["xyz"], b["q"], b["rho"], b["screen"], b["sigma"], b["eps"])
+    a = oracle.gradient(*args, oracle.obc2(kappa=0.1))
+    c = oracle.gradient(*args, oracle.obc2(kappa=0.1, cut=1e3, rgbmax=1e3))
+    for u, v in zip(a, c):
+        assert np.array_equal(u, v)
+
+
+def test_gradients_with_salt_and_cutoffs_match_central_differences():
+    """kappa = 0.15 / A, cut near 9 A, rgbmax near 11 A on a 64-atom system,
+    each moved by a few hundredths until no pair lies within 2e-3 A of it (the
+    truncated energy is smooth there): positions, charges and intrinsic radii
+    against central differences."""
+    b = _c0_small(64, seed=15)
+    x = b["xyz"].astype(np.float64)
+    q, rho = b["q"].astype(np.float64), b["rho"].astype(np.float64)
+    scr, sig, eps = b["screen"], b["sigma"], b["eps"]
+    r = np.sqrt(((x[:, None] - x[None]) ** 2).sum(-1))
+    clear = lambda c: np.abs(r - c).min() > 2e-3
+    cut = next(c for c in 9.0 + 0.01 * np.arange(50) if clear(c))
+    rgb = next(c for c in 11.0 + 0.01 * np.arange(50) if clear(c))
+    gb = oracle.obc2(kappa=0.15, cut=cut, rgbmax=rgb)
+    E, gx, gq, gr = oracle.gradient(x, q, rho, scr, sig, eps, gb)
+    tot = lambda xx, qq, rr: oracle.energy(xx, qq, rr, scr, sig, eps, gb).sum()
+    rng = np.random.default_rng(6)
+    for a in rng.choice(64, size=8, replace=False):
+        for c in range(3):
+            h = 1e-5
+            xp, xm = x.copy(), x.copy()
+            xp[a, c] += h; xm[a, c] -= h
+            fd = (tot(xp, q, rho) - tot(xm, q, rho)) / (2 * h)
+            assert fd == pytest.approx(gx[a, c], rel=1e-6, abs=1e-6 * np.abs(gx).max())
+        h = 1e-5
+        qp, qm = q.copy(), q.copy()
+        qp[a] += h; qm[a] -= h
+        fd = (tot(x, qp, rho) - tot(x, qm, rho)) / (2 * h)
+        assert fd == pytest.approx(gq[a], rel=1e-6, abs=1e-6 * np.abs(gq).max())
+        rp, rm = rho.copy(), rho.copy()
+        rp[a] += h; rm[a] -= h
+        fd = (tot(x, q, rp) - tot(x, q, rm)) / (2 * h)
+        assert fd == pytest.approx(gr[a], rel=1e-5, abs=1e-6 * np.abs(gr).max())
+
+
+def test_incremental_delta_e_with_salt_and_cutoff_equals_full_difference():
+    b = synth.make_config(1, n_atoms=200, n_rep=1, seed=22)
+    x, q = b["xyz"], b["q"].astype(np.float64)
+    gb = oracle.obc2(kappa=0.2, cut=8.0, rgbmax=10.0)
+    _, R, _ = oracle.born(x, b["rho"], b["screen"], gb)
+    E = abs(oracle.elec_energy(x, q, R, gb))
+    ms = b["max_states"]
+    for s in range(b["n_sites"]):
+        a, c = b["site_off"][s], b["site_off"][s + 1]
+        idx = b["site_atoms"][a:c]
+        qn = b["state_q"].reshape(-1, ms)[a:c, 1]
+        d_plain = oracle.delta_e(x, q, R, idx, qn, gb)
+        d_incr = oracle.delta_e(x, q, R, idx, qn, gb, incremental=True)
+        assert abs(d_plain - d_incr) <= 1e-9 * E
+        assert abs(d_plain) > 1e-3
+
+
 # ------------------------------- P10: Henderson-Hasselbalch / Nernst by MC
 def _frozen_site_batch(site_type, value, seed=31):
     """One isolated site (its atoms only), frozen (dt = 0), MC every step."""
