@@ -98,13 +98,23 @@ typedef struct gbr_ctx gbr_ctx;
 
 /* Generalized Born model constants.  OBC-II (igb=2): k_e = 332.0522173,
  * eps_in = 1, eps_out = 78.5, offset = 0.09 A, (alpha, beta, gamma) =
- * (1.0, 0.8, 4.85). */
+ * (1.0, 0.8, 4.85).  Optional (0 = off, the paper's setting):
+ *   kappa  Debye-Hueckel screening of the GB term: a GB pair term is
+ *          -k_e q_i q_j g(f_ij), a self term -(1/2) k_e q_i^2 g(R_i), with
+ *          g(f) = (1/eps_in - exp(-kappa f)/eps_out) / f;
+ *   cut    pairs at r >= cut drop out of the Coulomb, GB and LJ energies and
+ *          of the titration energy changes (plain truncation);
+ *   rgbmax pairs at r >= rgbmax drop out of the descreening sum.
+ * Self terms always stay.  Forces are the gradients of the truncated sums. */
 typedef struct {
     double k_e;       /* Coulomb constant, kcal A / (mol e^2)  */
     double eps_in;    /* solute dielectric                      */
     double eps_out;   /* solvent dielectric                     */
     double offset;    /* dielectric offset delta (A)            */
     double alpha, beta, gamma;
+    double kappa;     /* 1/A, >= 0                              */
+    double cut;       /* A, >= 0                                */
+    double rgbmax;    /* A, >= 0                                */
 } gbr_gb_params;
 
 /* Titratable sites (Theory, C(pH,E)MD: a residue's protonation or redox state

@@ -33,12 +33,15 @@ EXPORTED = ("gbr_ctx_create", "gbr_ctx_destroy", "gbr_check", "gbr_last_error", 
 class GBParams(C.Structure):
     _fields_ = [("k_e", C.c_double), ("eps_in", C.c_double), ("eps_out", C.c_double),
                 ("offset", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
-                ("gamma", C.c_double)]
+                ("gamma", C.c_double), ("kappa", C.c_double), ("cut", C.c_double),
+                ("rgbmax", C.c_double)]
 
 
-def obc2() -> GBParams:
-    """OBC-II (igb=2) constants."""
-    return GBParams(332.0522173, 1.0, 78.5, 0.09, 1.0, 0.8, 4.85)
+def obc2(kappa=0.0, cut=0.0, rgbmax=0.0) -> GBParams:
+    """OBC-II (igb=2) constants; kappa (1/A) screens the GB term with salt,
+    cut and rgbmax (A) truncate the pair energies and the descreening sum
+    (0: off)."""
+    return GBParams(332.0522173, 1.0, 78.5, 0.09, 1.0, 0.8, 4.85, kappa, cut, rgbmax)
 
 
 _vp = C.c_void_p

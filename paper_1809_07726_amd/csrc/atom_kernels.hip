@@ -48,14 +48,15 @@ __global__ __launch_bounds__(256) void k_born_finalize(
     if (psi_out) psi_out[a] = ps;
 }
 
-// dE/dR_i = pair part + (1/2) k_e tau q_i^2 / R_i^2;  c_i = dE/dR_i * dR_i/dpsi_i * rho~_i/2;
-// E_GB self = -(1/2) k_e tau q_i^2 / R_i added to the replica's energy;
-// dE/dq_i self = -k_e tau q_i / R_i.
+// With kg(R) = k_e g(R) = (k_e tau + (k_e/eps_out)(1 - exp(-kappa R))) / R (tau/R
+// without salt): dE/dR_i = pair part - (1/2) q_i^2 kg'(R_i);
+// c_i = dE/dR_i * dR_i/dpsi_i * rho~_i/2; E_GB self = -(1/2) q_i^2 kg(R_i) added
+// to the replica's energy; dE/dq_i self = -q_i kg(R_i).
 __global__ __launch_bounds__(256) void k_coef(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
     const float* __restrict__ q, const float* __restrict__ rho, const float* __restrict__ R,
     const float* __restrict__ dRdpsi, const int64_t* __restrict__ dEdR_fx, double ketau,
-    double offset, double* __restrict__ dEdR, float* __restrict__ cc,
+    double keout, double kappa, double offset, double* __restrict__ dEdR, float* __restrict__ cc,
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint64_t* __restrict__ step,
     uint32_t* __restrict__ err)
 {
@@ -72,11 +73,17 @@ __global__ __launch_bounds__(256) void k_coef(
     if (li < n) {
         const int a = a0 + li;
         const double qa = q[a], Ra = R[a];
-        const double g = from_fixed(dEdR_fx[a], INV_FX_FORCE) + 0.5 * ketau * qa * qa / (Ra * Ra);
+        double kg = ketau / Ra, dkg = -ketau / (Ra * Ra);
+        if (kappa > 0.0) {
+            const double es = exp(-kappa * Ra);
+            kg = (ketau + keout * (1.0 - es)) / Ra;
+            dkg = -kg / Ra + keout * kappa * es / Ra;
+        }
+        const double g = from_fixed(dEdR_fx[a], INV_FX_FORCE) - 0.5 * qa * qa * dkg;
         dEdR[a] = g;
         cc[a] = (float)(g * (double)dRdpsi[a] * 0.5 * ((double)rho[a] - offset));
-        eself = -0.5 * ketau * qa * qa / Ra;
-        if (dEdq_fx) dEdq_fx[a] += to_fixed(-ketau * qa / Ra, FX_FORCE, err);
+        eself = -0.5 * qa * qa * kg;
+        if (dEdq_fx) dEdq_fx[a] += to_fixed(-qa * kg, FX_FORCE, err);
     }
     const double s = wave_sum_d(eself);
     if (lane == 0) atomic_add_fx(&energy_fx[4 * tl.x], to_fixed(s, FX_ENERGY, err));
@@ -170,7 +177,8 @@ hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const
                        hipStream_t s) {
     const GBConstH k = make_const(c->prm);
     hipLaunchKernelGGL(k_coef, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
-                       c->atom_off, q, rho, R, dRdpsi, c->dEdR_fx, k.ke_d * k.tau_d, c->prm.offset,
+                       c->atom_off, q, rho, R, dRdpsi, c->dEdR_fx, k.ke_d * k.tau_d,
+                       c->prm.k_e / c->prm.eps_out, c->prm.kappa, c->prm.offset,
                        c->dEdR, c->chain_c, energy_fx, dEdq_fx, step, c->err);
     return hipGetLastError();
 }

@@ -252,6 +252,9 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     const gbr_gb_params& p = *params;
     if (!(p.k_e > 0) || !(p.eps_in > 0) || !(p.eps_out > 0) || !(p.offset >= 0))
         return fail(GBR_E_INVAL, "GB parameters out of range");
+    if (!(p.kappa >= 0 && p.kappa <= 100) || !(p.cut >= 0 && p.cut <= 1e6) ||
+        !(p.rgbmax >= 0 && p.rgbmax <= 1e6))
+        return fail(GBR_E_INVAL, "kappa, cut and rgbmax must be finite and >= 0");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(GBR_E_NODEVICE, "no HIP device");

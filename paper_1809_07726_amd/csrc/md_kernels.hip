@@ -1,6 +1,8 @@
 // md_kernels.hip -- the cheap O(N) and O(R) parts of a C(pH,E)MD / REMD
 // step that stay on the device: the BAOAB Langevin updates, the tether, the
 // titration Monte Carlo attempts, and the replica-exchange attempts.
+#include <cfloat>
+
 #include "gbr_device.h"
 #include "gbr_internal.h"
 
@@ -148,9 +150,25 @@ __device__ double block_sum_d(double v, double* red) {
     return s;
 }
 
+// Salt and the pair cutoff in the titration kernel: keout = k_e / eps_out,
+// kappa (1/A, 0: no salt), cut2 = cut^2 (FLT_MAX: no cutoff).
+struct Screening {
+    float keout, kappa, cut2;
+};
+
+// k_e g(f) of the GB term: (k_e tau + (k_e/eps_out)(1 - exp(-kappa f))) / f, given
+// 1/f; k_e tau / f without salt.
+__device__ __forceinline__ float kg_of(float finv, float ketau, const Screening& sc) {
+    if (sc.kappa > 0.0f) {
+        const float es = fexp_neg(sc.kappa / finv);
+        return (ketau + sc.keout * (1.0f - es)) * finv;
+    }
+    return ketau * finv;
+}
+
 __device__ double site_delta_e(SiteSmem& sm, int m, int a0, int n, int ntot,
                                const float* __restrict__ xyz, const float* __restrict__ q,
-                               const float* __restrict__ R, float ke_in, float ketau)
+                               const float* __restrict__ R, float ke_in, float ketau, Screening sc)
 {
     float lin = 0.0f;
     for (int j = a0 + (int)threadIdx.x; j < a0 + n; j += blockDim.x) {
@@ -160,14 +178,14 @@ __device__ double site_delta_e(SiteSmem& sm, int m, int a0, int n, int ntot,
         for (int k = 0; k < m; ++k) {
             float K;
             if (sm.atom[k] == j) {
-                K = -ketau / Rj;
+                K = -kg_of(1.0f / Rj, ketau, sc);
             } else {
                 const float dx = xj - sm.x[k], dy = yj - sm.y[k], dz = zj - sm.z[k];
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = frsq(r2);
                 const float ex = fexp_neg(0.25f * r2 / (sm.R[k] * Rj));
                 const float finv = frsq(__builtin_fmaf(sm.R[k] * Rj, ex, r2));
-                K = ke_in * rinv - ketau * finv;
+                K = (r2 < sc.cut2) ? ke_in * rinv - kg_of(finv, ketau, sc) : 0.0f;
             }
             acc += sm.d[k] * K;
         }
@@ -178,14 +196,14 @@ __device__ double site_delta_e(SiteSmem& sm, int m, int a0, int n, int ntot,
         const int k = t / m, l = t % m;
         float K;
         if (k == l) {
-            K = -ketau / sm.R[k];
+            K = -kg_of(1.0f / sm.R[k], ketau, sc);
         } else {
             const float dx = sm.x[l] - sm.x[k], dy = sm.y[l] - sm.y[k], dz = sm.z[l] - sm.z[k];
             const float r2 = dx * dx + dy * dy + dz * dz;
             const float rinv = frsq(r2);
             const float ex = fexp_neg(0.25f * r2 / (sm.R[k] * sm.R[l]));
             const float finv = frsq(__builtin_fmaf(sm.R[k] * sm.R[l], ex, r2));
-            K = ke_in * rinv - ketau * finv;
+            K = (r2 < sc.cut2) ? ke_in * rinv - kg_of(finv, ketau, sc) : 0.0f;
         }
         quad += sm.d[k] * sm.d[l] * K;
     }
@@ -211,7 +229,7 @@ __device__ void load_site(SiteSmem& sm, int m, int slot0, int nw, int ms, int nt
 __global__ __launch_bounds__(TB) void k_titration(
     const int32_t* __restrict__ atom_off, int n_rep, int ntot, const float* __restrict__ xyz,
     const float* __restrict__ q, const float* __restrict__ R, gbr_sites S,
-    const int32_t* __restrict__ cand, int n_cand, float ke_in, float ketau,
+    const int32_t* __restrict__ cand, int n_cand, float ke_in, float ketau, Screening sc,
     double* __restrict__ dE, uint32_t* __restrict__ err)
 {
     __shared__ SiteSmem sm;
@@ -234,7 +252,7 @@ __global__ __launch_bounds__(TB) void k_titration(
     }
     load_site(sm, m, S.site_off[site], nw, S.max_states, ntot, S.site_atoms, S.state_q, xyz, q, R);
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
-    const double v = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau);
+    const double v = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau, sc);
     if (threadIdx.x == 0) dE[c] = v;
 }
 
@@ -248,7 +266,7 @@ __global__ __launch_bounds__(TB) void k_mc(
     uint64_t seed, const float* __restrict__ xyz, float* __restrict__ q,
     const float* __restrict__ R, gbr_sites S, gbr_grid G, int32_t* __restrict__ site_state,
     const int32_t* __restrict__ target_idx, uint32_t* __restrict__ mc_stats, float ke_in,
-    float ketau, uint32_t* __restrict__ err)
+    float ketau, Screening sc, uint32_t* __restrict__ err)
 {
     __shared__ SiteSmem sm;
     __shared__ int s_site, s_new, s_acc;
@@ -289,7 +307,7 @@ __global__ __launch_bounds__(TB) void k_mc(
         const int nw = s_new;
         const int m = S.site_off[site + 1] - S.site_off[site];
         load_site(sm, m, S.site_off[site], nw, ms, ntot, S.site_atoms, S.state_q, xyz, q, R);
-        const double dEel = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau);
+        const double dEel = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau, sc);
         if (threadIdx.x == 0) {
             const int cur = site_state[site];
             const double T = G.T_vals[target_idx[3 * rep + 2]];
@@ -476,12 +494,20 @@ hipError_t launch_ke_out(const gbr_ctx* c, double* ke, hipStream_t s) {
     return hipGetLastError();
 }
 
+Screening make_screening(const gbr_gb_params& p) {
+    Screening sc;
+    sc.keout = (float)(p.k_e / p.eps_out);
+    sc.kappa = (float)p.kappa;
+    sc.cut2 = p.cut > 0 ? (float)(p.cut * p.cut) : FLT_MAX;
+    return sc;
+}
+
 hipError_t launch_mc(const gbr_ctx* c, const MDArgs& a, hipStream_t s) {
     const GBConstH k = make_const(c->prm);
     hipLaunchKernelGGL(k_mc, dim3(c->n_rep), dim3(TB), 0, s, c->atom_off, c->n_rep, c->n_atoms,
                        c->step, a.seed, a.st.xyz, a.st.q, a.st.R, a.pr.sites, a.pr.grid,
                        a.st.site_state, a.st.target_idx, a.st.mc_stats, k.ke_in,
-                       (float)(k.ke_d * k.tau_d), c->err);
+                       (float)(k.ke_d * k.tau_d), make_screening(c->prm), c->err);
     return hipGetLastError();
 }
 
@@ -492,7 +518,7 @@ hipError_t launch_titration(const gbr_ctx* c, const float* xyz, const float* q, 
     const GBConstH k = make_const(c->prm);
     hipLaunchKernelGGL(k_titration, dim3(n_cand), dim3(TB), 0, s, c->atom_off, c->n_rep,
                        c->n_atoms, xyz, q, R, sites, cand, n_cand, k.ke_in,
-                       (float)(k.ke_d * k.tau_d), dE, c->err);
+                       (float)(k.ke_d * k.tau_d), make_screening(c->prm), dE, c->err);
     return hipGetLastError();
 }
 

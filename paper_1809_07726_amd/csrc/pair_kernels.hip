@@ -27,6 +27,7 @@
 // Items are visited grid-stride by a persistent grid whose block index is
 // remapped so that the blocks of one XCD (blocks are dealt round-robin to the
 // eight XCDs) walk a contiguous range of the item list, i.e. of replicas.
+#include <cfloat>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -172,11 +173,11 @@ __device__ __forceinline__ bool both_far(float r, float mi, float mj, float sxi,
 // ------------------------------------------------------------- descreening
 // Distant spheres: h = (x^3/r) G(x^2) with x = s/r, i.e. h = s^3 r^-4 G(s^2 r^-2).
 // j tile in LDS: {x, y, z, s}, {rt, m, sx, s^3}
-template <int NI>
+template <int NI, bool EXT>
 __global__ __launch_bounds__(256) void k_born_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ rho,
-    const float* __restrict__ screen, float offset, int64_t* __restrict__ psi_fx,
+    const float* __restrict__ screen, float offset, PairExt ext, int64_t* __restrict__ psi_fx,
     uint32_t* __restrict__ err)
 {
     constexpr int NSL = NI == 2 ? 2 : 1;           // j tiles per wavefront
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
             const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
             float r2 = dx * dx + dy * dy + dz * dz;
             if (!FULL) r2 = ok ? r2 : FAR_R2;
+            if (EXT) r2 = r2 < ext.rgb2 ? r2 : FAR_R2;      // descreening cutoff
             const float rinv = frsq(r2);
             const float rinv2 = rinv * rinv;
             const float rinv4 = rinv2 * rinv2;
@@ -295,11 +297,11 @@ struct EnergyJ {
     float x, y, z, R, q;
 };
 
-template <int NI, bool GQ>
+template <int NI, bool GQ, bool EXT>
 __global__ __launch_bounds__(256) void k_energy_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ q, const float* __restrict__ Rb,
-    const float* __restrict__ sigma, const float* __restrict__ eps, float sq_ke_in, float taup,
+    const float* __restrict__ sigma, const float* __restrict__ eps, float sq_ke_in, float taup, PairExt ext,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdR_fx,
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
@@ -344,9 +346,9 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         // written (first) or added into c
         auto pair = [&](int u, const float4& p0, const float4& p1, bool ok, auto full, EnergyJ& c, bool first) {
             constexpr bool FULL = decltype(full)::value;
-            const bool valid = FULL || ok;
             const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
             const float r2 = dx * dx + dy * dy + dz * dz;
+            const bool valid = (FULL || ok) && (!EXT || r2 < ext.cut2);   // pair cutoff
             const float rinv = valid ? frsq(r2) : 0.0f;
             const float rinv2 = rinv * rinv;
             const float qq = qi[u] * p0.w;
@@ -355,8 +357,18 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             const float ex = __builtin_amdgcn_exp2f(-D2);   // exp(-D)
             const float f2 = __builtin_fmaf(Ri[u] * p1.x, ex, r2);
             const float finv = valid ? frsq(f2) : 0.0f;
-            const float eg = qq * finv;
+            float eg = qq * finv;
             const float t = eg * finv * finv;               // qq / f^3
+            // salt: the GB factor tau' becomes gsc = 1 - a exp(-kappa f) in the
+            // energy and G1 = gsc - a kappa f exp(-kappa f) in its f-derivative
+            float gsc = taup, G1 = taup;
+            if (EXT) {
+                const float f = f2 * finv;
+                const float es = __builtin_amdgcn_exp2f(-ext.kl2e * f);
+                gsc = __builtin_fmaf(ext.a, 1.0f - es, taup);
+                G1 = __builtin_fmaf(-ext.ak * es, f, gsc);
+                eg *= gsc;
+            }
             const float sgr = (hsi[u] + p1.z) * rinv;
             const float s2 = sgr * sgr;
             const float s6 = s2 * s2 * s2;
@@ -364,9 +376,11 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             const float B = A * s6;                         // 4 eps_ij s^12
             const float elj = B - A;
             const float uu = __builtin_fmaf(6.0f, B + elj, ec);
-            const float w = __builtin_fmaf(ex, wq, taup);   // tau' (1 - exp(-D)/4)
+            const float w = EXT ? G1 * __builtin_fmaf(ex, -0.25f, 1.0f)
+                                : __builtin_fmaf(ex, wq, taup);   // tau' (1 - exp(-D)/4)
             const float fs = __builtin_fmaf(-uu, rinv2, t * w);
-            const float gR = t * ex * __builtin_fmaf(D2, hl, 0.5f);
+            float gR = t * ex * __builtin_fmaf(D2, hl, 0.5f);
+            if (EXT) gR *= G1;
             e_c += ec;
             e_g += eg;
             e_lj += elj;
@@ -383,7 +397,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
                 c.R = __builtin_fmaf(gR, Ri[u], c.R);
             }
             if (GQ) {
-                const float wqq = __builtin_fmaf(-taup, finv, rinv);
+                const float wqq = __builtin_fmaf(-gsc, finv, rinv);
                 dqi[u] = __builtin_fmaf(wqq, p0.w, dqi[u]);
                 c.q = first ? wqq * qi[u] : __builtin_fmaf(wqq, qi[u], c.q);
             }
@@ -434,7 +448,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
                 atomic_add_fx(&force_fx[a], to_fixed_f(fxi[u], FXF_FORCE, err));
                 atomic_add_fx(&force_fx[ntot + a], to_fixed_f(fyi[u], FXF_FORCE, err));
                 atomic_add_fx(&force_fx[2 * ntot + a], to_fixed_f(fzi[u], FXF_FORCE, err));
-                atomic_add_fx(&dEdR_fx[a], to_fixed_f(dRi[u] * taup, FXF_FORCE, err));
+                atomic_add_fx(&dEdR_fx[a], to_fixed_f(EXT ? dRi[u] : dRi[u] * taup, FXF_FORCE, err));
                 if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed_f(dqi[u] * sq_ke_in, FXF_FORCE, err));
             }
         }
@@ -444,14 +458,14 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             atomic_add_fx(&force_fx[a], to_fixed_f(aj.x, FXF_FORCE, err));
             atomic_add_fx(&force_fx[ntot + a], to_fixed_f(aj.y, FXF_FORCE, err));
             atomic_add_fx(&force_fx[2 * ntot + a], to_fixed_f(aj.z, FXF_FORCE, err));
-            atomic_add_fx(&dEdR_fx[a], to_fixed_f(aj.R * taup, FXF_FORCE, err));
+            atomic_add_fx(&dEdR_fx[a], to_fixed_f(EXT ? aj.R : aj.R * taup, FXF_FORCE, err));
             if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed_f(aj.q * sq_ke_in, FXF_FORCE, err));
         };
         flush_j(g.jbase + ((lane + g.k1) & 63), accj[0]);
         if (NSL > 1 && g.diag && g.u_lim > 1)
             flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
         // per-lane energies to fixed point, summed over the wavefront as integers
-        const long long sgb = wave_sum_i64_lane63(to_fixed_f(-taup * e_g, FXF_ENERGY, err));
+        const long long sgb = wave_sum_i64_lane63(to_fixed_f(EXT ? -e_g : -taup * e_g, FXF_ENERGY, err));
         const long long sc = wave_sum_i64_lane63(to_fixed_f(e_c, FXF_ENERGY, err));
         const long long slj = wave_sum_i64_lane63(to_fixed_f(e_lj, FXF_ENERGY, err));
         if (lane == 63) {
@@ -473,11 +487,11 @@ struct ChainJ {
     float x, y, z, r;
 };
 
-template <int NI, bool RHO>
+template <int NI, bool RHO, bool EXT>
 __global__ __launch_bounds__(256) void k_chain_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ rho,
-    const float* __restrict__ screen, const float* __restrict__ cc, float offset,
+    const float* __restrict__ screen, const float* __restrict__ cc, float offset, PairExt ext,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdrho_fx, uint32_t* __restrict__ err)
 {
     constexpr int NSL = NI == 2 ? 2 : 1;
@@ -524,6 +538,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
             const float dx = p0.x - xi[u], dy = p0.y - yi[u], dz = p0.z - zi[u];
             float r2 = dx * dx + dy * dy + dz * dz;
             if (!FULL) r2 = ok ? r2 : FAR_R2;
+            if (EXT) r2 = r2 < ext.rgb2 ? r2 : FAR_R2;      // descreening cutoff
             const float rinv = frsq(r2);
             const float r = r2 * rinv;
             const float rinv2 = rinv * rinv;
@@ -649,6 +664,20 @@ const PairList& list_for(const gbr_ctx* c, int ni) {
 
 namespace gbr {
 
+PairExt make_pair_ext(const gbr_gb_params& p) {
+    PairExt e;
+    e.kl2e = (float)(p.kappa * 1.4426950408889634);
+    e.a = (float)(p.eps_in / p.eps_out);
+    e.ak = (float)(p.eps_in / p.eps_out * p.kappa);
+    e.cut2 = p.cut > 0 ? (float)(p.cut * p.cut) : FLT_MAX;
+    e.rgb2 = p.rgbmax > 0 ? (float)(p.rgbmax * p.rgbmax) : FLT_MAX;
+    return e;
+}
+
+static bool uses_ext(const gbr_ctx* c) {
+    return c->prm.kappa > 0 || c->prm.cut > 0 || c->prm.rgbmax > 0;
+}
+
 hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho,
                             const float* screen, hipStream_t s, LaunchEvents ev)
 {
@@ -656,13 +685,15 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
     const float off = (float)c->prm.offset;
-#define GBR_BORN(NI) hipExtLaunchKernelGGL(k_born_pair<NI>, grid, block, 0, s, ev.start, ev.stop, 0, L.items, L.n_items, \
-        c->atom_off, c->n_atoms, xyz, rho, screen, off, c->psi_fx, c->err)
+    const PairExt pe = make_pair_ext(c->prm);
+    const bool ext = uses_ext(c);
+#define GBR_BORN(NI, EX) hipExtLaunchKernelGGL((k_born_pair<NI, EX>), grid, block, 0, s, ev.start, ev.stop, 0, \
+        L.items, L.n_items, c->atom_off, c->n_atoms, xyz, rho, screen, off, pe, c->psi_fx, c->err)
     switch (L.ni) {
-        case 1: GBR_BORN(1); break;
-        case 2: GBR_BORN(2); break;
-        case 4: GBR_BORN(4); break;
-        default: GBR_BORN(8); break;
+        case 1: if (ext) GBR_BORN(1, true); else GBR_BORN(1, false); break;
+        case 2: if (ext) GBR_BORN(2, true); else GBR_BORN(2, false); break;
+        case 4: if (ext) GBR_BORN(4, true); else GBR_BORN(4, false); break;
+        default: if (ext) GBR_BORN(8, true); else GBR_BORN(8, false); break;
     }
 #undef GBR_BORN
     return hipGetLastError();
@@ -678,16 +709,19 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
     const float sq = (float)sqrt(c->prm.k_e / c->prm.eps_in);
     const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
-#define GBR_EN(NI, GQ) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ>), grid, block, 0, s, ev.start, ev.stop, 0, L.items, \
-        L.n_items, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, force_fx, \
-        c->dEdR_fx, energy_fx, dEdq_fx, c->err)
+    const PairExt pe = make_pair_ext(c->prm);
+#define GBR_EN(NI, GQ, EX) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ, EX>), grid, block, 0, s, ev.start, \
+        ev.stop, 0, L.items, L.n_items, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, pe, \
+        force_fx, c->dEdR_fx, energy_fx, dEdq_fx, c->err)
+#define GBR_EN2(NI, GQ) if (uses_ext(c)) GBR_EN(NI, GQ, true); else GBR_EN(NI, GQ, false)
     const bool gq = dEdq_fx != nullptr;
     switch (L.ni) {
-        case 1: if (gq) GBR_EN(1, true); else GBR_EN(1, false); break;
-        case 2: if (gq) GBR_EN(2, true); else GBR_EN(2, false); break;
-        case 4: if (gq) GBR_EN(4, true); else GBR_EN(4, false); break;
-        default: if (gq) GBR_EN(8, true); else GBR_EN(8, false); break;
+        case 1: if (gq) { GBR_EN2(1, true); } else { GBR_EN2(1, false); } break;
+        case 2: if (gq) { GBR_EN2(2, true); } else { GBR_EN2(2, false); } break;
+        case 4: if (gq) { GBR_EN2(4, true); } else { GBR_EN2(4, false); } break;
+        default: if (gq) { GBR_EN2(8, true); } else { GBR_EN2(8, false); } break;
     }
+#undef GBR_EN2
 #undef GBR_EN
     return hipGetLastError();
 }
@@ -700,16 +734,19 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
     const float off = (float)c->prm.offset;
-#define GBR_CH(NI, RH) hipExtLaunchKernelGGL((k_chain_pair<NI, RH>), grid, block, 0, s, ev.start, ev.stop, 0, L.items, \
-        L.n_items, c->atom_off, c->n_atoms, xyz, rho, screen, c->chain_c, off, force_fx, \
-        dEdrho_fx, c->err)
+    const PairExt pe = make_pair_ext(c->prm);
+#define GBR_CH(NI, RH, EX) hipExtLaunchKernelGGL((k_chain_pair<NI, RH, EX>), grid, block, 0, s, ev.start, \
+        ev.stop, 0, L.items, L.n_items, c->atom_off, c->n_atoms, xyz, rho, screen, c->chain_c, off, pe, \
+        force_fx, dEdrho_fx, c->err)
+#define GBR_CH2(NI, RH) if (uses_ext(c)) GBR_CH(NI, RH, true); else GBR_CH(NI, RH, false)
     const bool rh = dEdrho_fx != nullptr;
     switch (L.ni) {
-        case 1: if (rh) GBR_CH(1, true); else GBR_CH(1, false); break;
-        case 2: if (rh) GBR_CH(2, true); else GBR_CH(2, false); break;
-        case 4: if (rh) GBR_CH(4, true); else GBR_CH(4, false); break;
-        default: if (rh) GBR_CH(8, true); else GBR_CH(8, false); break;
+        case 1: if (rh) { GBR_CH2(1, true); } else { GBR_CH2(1, false); } break;
+        case 2: if (rh) { GBR_CH2(2, true); } else { GBR_CH2(2, false); } break;
+        case 4: if (rh) { GBR_CH2(4, true); } else { GBR_CH2(4, false); } break;
+        default: if (rh) { GBR_CH2(8, true); } else { GBR_CH2(8, false); } break;
     }
+#undef GBR_CH2
 #undef GBR_CH
     return hipGetLastError();
 }

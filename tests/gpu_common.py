@@ -21,10 +21,10 @@ def soa_to_aos(x, n):
     return np.asarray(x, dtype=np.float64).reshape(3, n).T
 
 
-def gpu_eval(b, grad_q=False, grad_rho=False, blocking=None, launch=None):
+def gpu_eval(b, grad_q=False, grad_rho=False, blocking=None, launch=None, params=None):
     """Born radii, energies and gradients of every replica on the GPU."""
     from paper_1809_07726_amd.gb import Context
-    ctx = Context(b["atom_off"])
+    ctx = Context(b["atom_off"], params)
     if blocking:
         ctx.set_blocking(*blocking)
     if launch:
@@ -50,3 +50,19 @@ def gpu_eval(b, grad_q=False, grad_rho=False, blocking=None, launch=None):
 
 def rms_rel(a, b):
     return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+def clear_cutoffs(b, cut0, rgb0, gap=5e-5):
+    """cut and rgbmax near the requested values, moved by steps of 0.013 A until
+    no pair of any replica lies within gap of either: a pair within FP32
+    rounding of a cutoff (about 1e-5 A at 10 A) may be counted on one side and
+    not on the other."""
+    off = b["atom_off"]
+    r = []
+    for k in range(off.size - 1):
+        x = b["xyz"][off[k]:off[k + 1]].astype(np.float64)
+        d = np.sqrt(((x[:, None] - x[None]) ** 2).sum(-1))
+        r.append(d[np.triu_indices(len(x), 1)])
+    r = np.concatenate(r)
+    pick = lambda c0: next(c for c in c0 + 0.013 * np.arange(200) if np.abs(r - c).min() > gap)
+    return pick(cut0), pick(rgb0)

@@ -17,9 +17,9 @@ from paper_1809_07726_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_md(b, seed, steps_chunks, graph=False, init=True):
+def _gpu_md(b, seed, steps_chunks, graph=False, init=True, params=None):
     from paper_1809_07726_amd.gb import MD, Context, DeviceBatch
-    ctx = Context(b["atom_off"])
+    ctx = Context(b["atom_off"], params)
     d = DeviceBatch.from_numpy(b)
     md = MD(ctx, d, b, seed=seed)
     snaps = []
@@ -45,8 +45,8 @@ def _gpu_md(b, seed, steps_chunks, graph=False, init=True):
     return snaps
 
 
-def _oracle_md(b, seed, steps_chunks):
-    cfg, st, arr, keep = oracle.make_md(b, seed=seed)
+def _oracle_md(b, seed, steps_chunks, gb=None):
+    cfg, st, arr, keep = oracle.make_md(b, gb=gb, seed=seed)
     oracle.md_run(cfg, st, 0, 0, True)
     snaps, step = [], 0
     for n in steps_chunks:
@@ -229,3 +229,33 @@ def test_gpu_three_state_site_statistics(d):
     for s in range(3):
         per_rep = (occ == s).mean(0)            # 64 independent chains
         assert abs(per_rep.mean() - p[s]) <= batch_mean_bound(per_rep, 16), (s, per_rep.mean(), p[s])
+
+
+def test_md_step_with_salt_and_cutoffs_matches_oracle():
+    """c0 with salt (kappa = 0.1 / A) and both cutoffs (near 9 and 11 A, clear of
+    every starting pair distance): one step from rest to FP32 rounding.  Then
+    25 steps with salt alone and titration attempts every 10 (with cutoffs, a
+    pair that the trajectory carries across a cutoff within FP32 rounding of
+    it may be counted at different steps on the two sides)."""
+    import paper_1809_07726_amd._capi as A
+    from gpu_common import clear_cutoffs
+    base = synth.make_config(0)
+    cut, rgb = clear_cutoffs(base, 9.0, 11.0)
+    P = A.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    G = oracle.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    b = with_oracle_gref(base, G)
+    g = _gpu_md(b, 78, [1], params=P)[0]
+    o = _oracle_md(b, 78, [1], gb=G)[0]
+    assert np.abs(g["xyz"] - o["xyz"].reshape(-1, 3)).max() < 1e-5
+    v_o = o["v"].reshape(-1, 3)
+    assert np.abs(g["v"] - v_o).max() < 1e-4 * np.abs(v_o).max()
+    P, G = A.obc2(kappa=0.1), oracle.obc2(kappa=0.1)
+    b = with_oracle_gref(base, G)
+    seed = 2200
+    g = _gpu_md(b, seed, [10, 15], params=P)
+    o = _oracle_md(b, seed, [10, 15], gb=G)
+    for gs, os_ in zip(g, o):
+        assert np.abs(gs["xyz"] - os_["xyz"].reshape(-1, 3)).max() < 2e-4
+        assert np.array_equal(gs["site_state"], os_["site_state"])
+        Eo = os_["E"].reshape(-1, 4)
+        assert np.allclose(gs["E"], Eo, rtol=1e-4, atol=1e-3)

@@ -5,16 +5,16 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import E_TOL, F_TOL, R_TOL, gpu_eval, rms_rel
+from gpu_common import E_TOL, F_TOL, R_TOL, clear_cutoffs, gpu_eval, rms_rel
 from paper_1809_07726_amd import synth
 
 pytestmark = pytest.mark.gpu
 
 
-def _oracle_batch(b, grads=True):
+def _oracle_batch(b, grads=True, gb=None):
     off = b["atom_off"]
-    E, gx, gq, gr = oracle.eval_batch(off, b["xyz"], b["q"], b["rho"], b["screen"], b["sigma"], b["eps"])
-    psi, R, _ = oracle.born_batch(off, b["xyz"], b["rho"], b["screen"])
+    E, gx, gq, gr = oracle.eval_batch(off, b["xyz"], b["q"], b["rho"], b["screen"], b["sigma"], b["eps"], gb)
+    psi, R, _ = oracle.born_batch(off, b["xyz"], b["rho"], b["screen"], gb)
     return {"E": E, "F": -gx, "dEdq": gq, "dEdrho": gr, "R": R, "psi": psi}
 
 
@@ -156,3 +156,57 @@ def test_titration_delta_e_for_every_state_of_three_state_sites():
         ref = oracle.delta_e(x, b["q"][a0:a1], Ro, idx, qn)
         scale = abs(oracle.elec_energy(x, b["q"][a0:a1], Ro)) / len(idx)
         assert abs(dE[i] - ref) <= 1e-6 * max(abs(ref), scale), (s, k, dE[i], ref)
+
+
+# --------------------------- salt screening and pair cutoffs (kappa, cut, rgbmax)
+@pytest.mark.parametrize("ni", [1, 2, 4, 8])
+@pytest.mark.parametrize("kappa,cut,rgb", [(0.15, 10.0, 12.0), (0.1, 0.0, 0.0), (0.0, 9.0, 0.0),
+                                           (0.0, 0.0, 8.0)])
+def test_salt_and_cutoffs_match_oracle(ni, kappa, cut, rgb):
+    """Energies, forces, dE/dq and dE/drho with salt and with either cutoff
+    alone or both, for every register blocking, against the oracle with the
+    same settings; and the settings do change the result."""
+    import paper_1809_07726_amd._capi as A
+    b = synth.make_config(1, n_atoms=700, n_rep=2, per_replica_jitter=True)
+    if cut or rgb:
+        c, g_ = clear_cutoffs(b, cut or 9.0, rgb or 9.0)
+        cut, rgb = (c if cut else 0.0), (g_ if rgb else 0.0)
+    P = A.obc2(kappa=kappa, cut=cut, rgbmax=rgb)
+    G = oracle.obc2(kappa=kappa, cut=cut, rgbmax=rgb)
+    g = gpu_eval(b, True, True, blocking=(ni, ni, ni), params=P)
+    o = _oracle_batch(b, gb=G)
+    _check(b, g, o, grads=True)
+    plain = _oracle_batch(b)
+    assert np.abs(plain["E"] - o["E"]).max() > 1e-3
+
+
+def test_titration_delta_e_with_salt_and_cutoff_matches_oracle():
+    import paper_1809_07726_amd._capi as A
+    import torch
+    from paper_1809_07726_amd.gb import Context
+    from gpu_common import to_dev
+    b = synth.make_config(1, n_rep=3, per_replica_jitter=True)
+    cut, rgb = clear_cutoffs(b, 9.0, 11.0)
+    P = A.obc2(kappa=0.2, cut=cut, rgbmax=rgb)
+    G = oracle.obc2(kappa=0.2, cut=cut, rgbmax=rgb)
+    d = to_dev(b)
+    ctx = Context(b["atom_off"], P)
+    t = d.t
+    R, _, _ = ctx.born_radii(t["xyz"], t["rho"], t["screen"])
+    cand = np.array([(s, 1) for s in range(b["n_sites"])], np.int32).reshape(-1)
+    dE = ctx.titration_delta_e(t["xyz"], t["q"], R, d, torch.as_tensor(cand)).cpu().numpy()
+    ctx.check()
+    ctx.close()
+    off = b["atom_off"]
+    ms = b["max_states"]
+    for s in range(b["n_sites"]):
+        r = int(np.searchsorted(off, b["site_atoms"][b["site_off"][s]], side="right") - 1)
+        a0, a1 = off[r], off[r + 1]
+        x = b["xyz"][a0:a1]
+        _, Ro, _ = oracle.born(x, b["rho"][a0:a1], b["screen"][a0:a1], G)
+        sl = slice(b["site_off"][s], b["site_off"][s + 1])
+        idx = b["site_atoms"][sl] - a0
+        qn = b["state_q"].reshape(-1, ms)[sl, 1]
+        ref = oracle.delta_e(x, b["q"][a0:a1], Ro, idx, qn, G)
+        scale = abs(oracle.elec_energy(x, b["q"][a0:a1], Ro, G)) / len(idx)
+        assert abs(dE[s] - ref) <= 1e-6 * max(abs(ref), scale), (s, dE[s], ref)
