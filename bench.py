@@ -71,9 +71,12 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel, launches_bytes_alg):
+def traffic_from_profile(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources; else None."""
+    summary (taken on the 192 x 1,024 batch), if it was taken on the current
+    kernel sources and the workload is that batch; else None."""
+    if not workload.startswith("c2_"):
+        return None
     path = os.path.join(ROOT, "profiles", "pair_kernels_c2_hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -84,7 +87,21 @@ def traffic_from_profile(kernel, launches_bytes_alg):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(b, n_rep_sample, gpu_ref=None, min_s=10.0, budget_s=20.0):
+def pair_counts(b, cut):
+    """Unordered pairs per replica: all of them, or those closer than cut."""
+    off = b["atom_off"]
+    n = np.diff(off).astype(np.int64)
+    if not cut:
+        return n * (n - 1) // 2
+    from scipy.spatial import cKDTree
+    out = np.zeros(n.size, np.int64)
+    for r in range(n.size):
+        tree = cKDTree(np.asarray(b["xyz"][off[r]:off[r + 1]], np.float64))
+        out[r] = (tree.count_neighbors(tree, np.nextafter(cut, 0.0)) - n[r]) // 2
+    return out
+
+
+def cpu_baseline(b, n_rep_sample, gpu_ref=None, ext=None, rep_pairs=None, min_s=10.0, budget_s=20.0):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
     full E+F gradient evaluations of successive replicas (cycling through the
     batch) until at least min_s seconds of CPU work, stopping at budget_s or
@@ -92,6 +109,7 @@ def cpu_baseline(b, n_rep_sample, gpu_ref=None, min_s=10.0, budget_s=20.0):
     the GPU's energies [n_rep, 5] and forces [N, 3] at the same inputs, also
     returns the GPU's error against FP64 on the replicas evaluated."""
     import oracle
+    gb = oracle.obc2(**(ext or {}))
     off = b["atom_off"]
     t0 = time.perf_counter()
     pairs = 0
@@ -105,11 +123,11 @@ def cpu_baseline(b, n_rep_sample, gpu_ref=None, min_s=10.0, budget_s=20.0):
         done += 1
         a, c = off[r], off[r + 1]
         E, gx, _, _ = oracle.gradient(b["xyz"][a:c], b["q"][a:c], b["rho"][a:c], b["screen"][a:c],
-                                      b["sigma"][a:c], b["eps"][a:c])
+                                      b["sigma"][a:c], b["eps"][a:c], gb)
         if r not in first:
             first[r] = (E, gx)
         n = c - a
-        pairs += n * (n - 1) // 2
+        pairs += int(rep_pairs[r]) if rep_pairs is not None else n * (n - 1) // 2
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
@@ -149,14 +167,20 @@ def main():
     from paper_1809_07726_amd.gb import MD, Context, DeviceBatch, reference_energies
     from paper_1809_07726_amd.tune import autotune
 
+    import paper_1809_07726_amd._capi as A
     torch.cuda.set_device(0)
     b = synth.make_config(args.config)
     w = synth.CONFIGS[args.config]
-    b["G_ref"] = reference_energies(b)
-    ctx = Context(b["atom_off"])
+    ext = {k: w.extra[k] for k in ("kappa", "cut", "rgbmax") if k in w.extra}
+    params = A.obc2(**ext)
+    b["G_ref"] = reference_energies(b, params)
+    ctx = Context(b["atom_off"], params)
     dev = DeviceBatch.from_numpy(b)
     md = MD(ctx, dev, b, seed=w.dyn_seed)
-    n_pairs = ctx.n_pairs
+    # a pair interaction: an unordered pair of one replica that the evaluation
+    # counts (with a cutoff: the pairs within it at the starting coordinates)
+    rep_pairs = pair_counts(b, ext.get("cut", 0.0))
+    n_pairs = int(rep_pairs.sum())
     stream = torch.cuda.current_stream()
 
     _progress(f"{w.name}: {b['n_rep']} replicas, {n_pairs} pairs per step; autotuning")
@@ -208,7 +232,7 @@ def main():
     if cnt:
         avg = ms / cnt
         ach = flops[dom] * n_pairs / (avg * 1e-3) / 1e12
-        traffic = traffic_from_profile(dom, None)
+        traffic = traffic_from_profile(dom, w.name)
         roofline = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
                     "traffic": traffic, "hbm_gbs": (traffic / (avg * 1e-3) / 1e9 if traffic else None),
@@ -265,7 +289,7 @@ def main():
         # one single-replica context per distinct replica size; the launch tuned
         # for the largest size is used for all of them
         sizes = np.diff(off).astype(int)
-        pctx = {int(n): Context(np.array([0, n], np.int32)) for n in np.unique(sizes)}
+        pctx = {int(n): Context(np.array([0, n], np.int32), params) for n in np.unique(sizes)}
         reps = []
         for r in range(b["n_rep"]):
             a, c = off[r], off[r + 1]
@@ -300,7 +324,7 @@ def main():
     cpu, err64 = None, None
     if not args.no_cpu_baseline:
         _progress("oracle CPU baseline")
-        cpu, err64 = cpu_baseline(b, args.cpu_sample_replicas, gpu_ref)
+        cpu, err64 = cpu_baseline(b, args.cpu_sample_replicas, gpu_ref, ext, rep_pairs)
 
     sizes = np.diff(b["atom_off"]).astype(int)
     atoms_per_replica = (int(sizes[0]) if np.all(sizes == sizes[0]) else
@@ -313,6 +337,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "replicas": int(b["n_rep"]), "atoms_per_replica": atoms_per_replica,
                    "grid": f"{len(w.E_vals)} E x {len(w.T_vals)} T x {len(w.pH_vals)} pH",
+                   "gb_extensions": ext or None,
                    "pairs_per_step": n_pairs, "mc_every": w.mc_every,
                    "ex_every": w.ex_every, "graph": bool(args.graph),
                    "accumulation": "int64 fixed point (forces 2^-40, energies 2^-32)",

@@ -124,7 +124,8 @@ int upload(void* dst, const void* src, size_t bytes) {
 // One force evaluation inside md_step (the caller has cleared the accumulators);
 // advance: the evaluation belongs to a step, whose counter then advances.
 int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, bool advance, hipStream_t s) {
-    hipError_t e;
+    hipError_t e = launch_cull(c, a.st.xyz, s);
+    if (e != hipSuccess) return hip_fail(e, "cull");
     {
         Timed t(c, GBR_K_BORN_PAIR, s, true);
         e = launch_born_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, s, t.ev);
@@ -301,6 +302,24 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
             (rc = upload(c->lists[k].items, items.data(), sizeof(int2) * items.size())))
             return done(rc);
     }
+    // with both cutoffs the pair passes run culled copies of the lists
+    c->cull = p.cut > 0 && p.rgbmax > 0;
+    if (c->cull) {
+        std::vector<int32_t> tb(n_rep);
+        for (int r = 0, t = 0; r < n_rep; ++r) {
+            tb[r] = t;
+            t += (atom_off_host[r + 1] - atom_off_host[r] + 63) / 64;
+        }
+        if ((rc = dev_alloc(&c->tile_base, n_rep))) return done(rc);
+        if ((rc = upload(c->tile_base, tb.data(), sizeof(int32_t) * n_rep))) return done(rc);
+        if ((rc = dev_alloc(&c->tile_box, 2 * (size_t)c->n_tiles))) return done(rc);
+        if ((rc = dev_alloc(&c->cull_count, 8))) return done(rc);
+        for (int k = 0; k < 4; ++k)
+            for (int v = 0; v < 2; ++v) {
+                if ((rc = dev_alloc(&c->lists[k].culled[v], (size_t)c->lists[k].n_items))) return done(rc);
+                c->lists[k].n_culled[v] = c->cull_count + 2 * k + v;
+            }
+    }
     // default register blocking: more i atoms per lane for larger replicas
     const int ni = max_n >= 4096 ? 8 : (max_n >= 512 ? 4 : (max_n >= 128 ? 2 : 1));
     c->ni_born = c->ni_energy = c->ni_chain = ni;
@@ -336,7 +355,10 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     for (auto& ev : c->timer.pool) if (ev) (void)hipEventDestroy(ev);
     (void)hipFree(c->atom_off);
     (void)hipFree(c->tiles);
-    for (auto& L : c->lists) (void)hipFree(L.items);
+    for (auto& L : c->lists) { (void)hipFree(L.items); (void)hipFree(L.culled[0]); (void)hipFree(L.culled[1]); }
+    (void)hipFree(c->tile_base);
+    (void)hipFree(c->tile_box);
+    (void)hipFree(c->cull_count);
     (void)hipFree(c->psi_fx); (void)hipFree(c->dEdR_fx); (void)hipFree(c->dEdR); (void)hipFree(c->chain_c);
     (void)hipFree(c->ke_fx); (void)hipFree(c->ex_nH); (void)hipFree(c->ex_ne); (void)hipFree(c->ex_eps);
     (void)hipFree(c->ex_vscale); (void)hipFree(c->step); (void)hipFree(c->err);
@@ -419,7 +441,8 @@ int gb_born_radii(gbr_ctx* c, const float* xyz, const float* rho, const float* s
                   float* dRdpsi, double* psi, hipStream_t s) {
     if (int rc = check_ctx(c)) return rc;
     REQ(xyz); REQ(rho); REQ(screen); REQ(R); REQ(dRdpsi);
-    hipError_t e = launch_zero_i64(c->psi_fx, c->n_atoms, s);
+    hipError_t e = launch_cull(c, xyz, s);
+    if (e == hipSuccess) e = launch_zero_i64(c->psi_fx, c->n_atoms, s);
     if (e != hipSuccess) return hip_fail(e, "zero");
     {
         Timed t(c, GBR_K_BORN_PAIR, s, true);
@@ -456,6 +479,7 @@ int gb_energy_forces(gbr_ctx* c, const float* xyz, const float* q, const float* 
         if (e == hipSuccess && gr) e = launch_zero_i64(dEdrho_fx, N, s);
     }
     if (e == hipSuccess) e = launch_zero_i64(c->dEdR_fx, N, s);
+    if (e == hipSuccess) e = launch_cull(c, xyz, s);
     if (e != hipSuccess) return hip_fail(e, "zero");
     {
         Timed t(c, GBR_K_ENERGY_PAIR, s, true);

@@ -17,6 +17,10 @@ struct PairList {
     int ni = 0;                // i atoms per lane the list was built for
     int2* items = nullptr;     // {rep | type << 30, (A << 16) | B}
     int32_t n_items = 0;
+    // with both cutoffs: the items whose tiles come within reach, for the
+    // descreening passes (rgbmax, [0]) and for the energy pass (cut, [1])
+    int2* culled[2] = {nullptr, nullptr};
+    int32_t* n_culled[2] = {nullptr, nullptr};   // their counts (device)
 };
 
 struct LaunchShape {
@@ -46,6 +50,10 @@ struct gbr_ctx {
     int2* tiles = nullptr;           // per-atom tiles {rep, tile}
     int32_t n_tiles = 0;
     gbr::PairList lists[4];          // NI = 1, 2, 4, 8
+    bool cull = false;               // both cutoffs set: the pair passes run culled lists
+    int32_t* tile_base = nullptr;    // [n_rep] index of each replica's first tile
+    float4* tile_box = nullptr;      // [2 n_tiles] per-tile bounding boxes (min, max)
+    int32_t* cull_count = nullptr;   // [8] survivors per list and radius
     int ni_born = 4, ni_energy = 4, ni_chain = 4;
     gbr::LaunchShape shape;
     // workspace
@@ -99,6 +107,12 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
 hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rho,
                              const float* screen, int64_t* force_fx, int64_t* dEdrho_fx,
                              hipStream_t s, LaunchEvents ev = {});
+
+// With both cutoffs: per-tile bounding boxes of xyz, then for every list in
+// use the block items whose I block and J tile come within rgbmax (for the
+// descreening passes) or cut (for the energy pass), and every triangle or
+// diagonal item, compacted into that list's culled copies.
+hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s);
 
 // per-atom kernels ------------------------------------------------------------
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);

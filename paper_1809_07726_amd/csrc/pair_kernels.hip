@@ -27,6 +27,7 @@
 // Items are visited grid-stride by a persistent grid whose block index is
 // remapped so that the blocks of one XCD (blocks are dealt round-robin to the
 // eight XCDs) walk a contiguous range of the item list, i.e. of replicas.
+#include <algorithm>
 #include <cfloat>
 #include <type_traits>
 
@@ -175,7 +176,8 @@ __device__ __forceinline__ bool both_far(float r, float mi, float mj, float sxi,
 // j tile in LDS: {x, y, z, s}, {rt, m, sx, s^3}
 template <int NI, bool EXT>
 __global__ __launch_bounds__(256) void k_born_pair(
-    const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
+    const int2* __restrict__ items, int n_items, const int32_t* __restrict__ n_dev,
+    const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ rho,
     const float* __restrict__ screen, float offset, PairExt ext, int64_t* __restrict__ psi_fx,
     uint32_t* __restrict__ err)
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
+    if (n_dev) n_items = n_dev[0];                // a culled list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
         const ItemGeom g = item_geom<NI>(items[it], atom_off);
         float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], s2i[NI], s3i[NI], mi[NI], sxi[NI], acc[NI];
@@ -299,7 +302,8 @@ struct EnergyJ {
 
 template <int NI, bool GQ, bool EXT>
 __global__ __launch_bounds__(256) void k_energy_pair(
-    const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
+    const int2* __restrict__ items, int n_items, const int32_t* __restrict__ n_dev,
+    const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ q, const float* __restrict__ Rb,
     const float* __restrict__ sigma, const float* __restrict__ eps, float sq_ke_in, float taup, PairExt ext,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdR_fx,
@@ -312,6 +316,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     const float lc = 0.60056120439322491f;       // sqrt(log2(e) / 4)
     const float hl = 0.5f / LOG2E;               // D = D2 / log2(e)
     const float wq = -0.25f * taup;
+    if (n_dev) n_items = n_dev[0];                // a culled list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
         const ItemGeom g = item_geom<NI>(items[it], atom_off);
         float xi[NI], yi[NI], zi[NI], qi[NI], Ri[NI], Li[NI], hsi[NI], sei[NI];
@@ -489,7 +494,8 @@ struct ChainJ {
 
 template <int NI, bool RHO, bool EXT>
 __global__ __launch_bounds__(256) void k_chain_pair(
-    const int2* __restrict__ items, int n_items, const int32_t* __restrict__ atom_off, int ntot,
+    const int2* __restrict__ items, int n_items, const int32_t* __restrict__ n_dev,
+    const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ rho,
     const float* __restrict__ screen, const float* __restrict__ cc, float offset, PairExt ext,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdrho_fx, uint32_t* __restrict__ err)
@@ -499,6 +505,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
+    if (n_dev) n_items = n_dev[0];                // a culled list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
         const ItemGeom g = item_geom<NI>(items[it], atom_off);
         float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], ci[NI], Si[NI], mi[NI], sxi[NI], s2i[NI], s3i[NI];
@@ -635,6 +642,79 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     }
 }
 
+// ------------------------------------------------------------- culling
+// Per-tile bounding boxes: one wavefront per tile, min / max over its atoms.
+// Also clears the four survivor counters (the culling kernels run after).
+__global__ __launch_bounds__(256) void k_tile_boxes(
+    const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
+    const float* __restrict__ xyz, float4* __restrict__ box, int32_t* __restrict__ counts)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 8) counts[threadIdx.x] = 0;
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
+    if (t >= n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int2 tl = tiles[t];
+    const int a0 = atom_off[tl.x], n = atom_off[tl.x + 1] - a0;
+    const int li = min(tl.y * 64 + lane, n - 1);        // the tail repeats the last atom
+    const int a = a0 + li;
+    float lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = xyz[(int64_t)d * ntot + a];
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fminf(lo[d], __shfl_xor(lo[d], off, 64));
+            hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], off, 64));
+        }
+    }
+    if (lane == 0) {
+        box[2 * t] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+        box[2 * t + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    }
+}
+
+// One thread per item of a list: block items whose I block (NI tiles) and J
+// tile boxes are farther apart than rc are dropped, the rest (and every
+// triangle or diagonal item) appended to the culled list, one atomic per
+// wavefront.  The culled order is arbitrary; the fixed-point sums do not
+// depend on it.
+__global__ __launch_bounds__(256) void k_cull(
+    const int2* __restrict__ items, int n_items, int ni, const int32_t* __restrict__ atom_off,
+    const int32_t* __restrict__ tile_base, const float4* __restrict__ box, float rc2,
+    int2* __restrict__ out, int32_t* __restrict__ count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool keep = false;
+    int2 wi = make_int2(0, 0);
+    if (i < n_items) {
+        wi = items[i];
+        keep = true;
+        if (((unsigned)wi.x >> 30) == (unsigned)ITEM_BLOCK) {
+            const int rep = wi.x & 0x3FFFFFF;
+            const int A = wi.y >> 16, B = wi.y & 0xFFFF;
+            const int T = (atom_off[rep + 1] - atom_off[rep] + 63) >> 6;
+            const int tb = tile_base[rep];
+            float4 ilo = box[2 * (tb + A * ni)], ihi = box[2 * (tb + A * ni) + 1];
+            for (int u = 1; u < ni && A * ni + u < T; ++u) {
+                const float4 l = box[2 * (tb + A * ni + u)], h = box[2 * (tb + A * ni + u) + 1];
+                ilo = make_float4(fminf(ilo.x, l.x), fminf(ilo.y, l.y), fminf(ilo.z, l.z), 0.0f);
+                ihi = make_float4(fmaxf(ihi.x, h.x), fmaxf(ihi.y, h.y), fmaxf(ihi.z, h.z), 0.0f);
+            }
+            const float4 jlo = box[2 * (tb + B)], jhi = box[2 * (tb + B) + 1];
+            const float dx = fmaxf(0.0f, fmaxf(ilo.x - jhi.x, jlo.x - ihi.x));
+            const float dy = fmaxf(0.0f, fmaxf(ilo.y - jhi.y, jlo.y - ihi.y));
+            const float dz = fmaxf(0.0f, fmaxf(ilo.z - jhi.z, jlo.z - ihi.z));
+            keep = dx * dx + dy * dy + dz * dz < rc2;
+        }
+    }
+    const unsigned long long m = __ballot(keep);
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, 0, 64);
+    if (keep) out[base + __popcll(m & ((1ull << lane) - 1ull))] = wi;
+}
+
 int grid_for(const gbr_ctx* c, int n_items) {
     const int W = c->shape.waves_per_group;
     int want = (n_items + W - 1) / W;
@@ -678,17 +758,42 @@ static bool uses_ext(const gbr_ctx* c) {
     return c->prm.kappa > 0 || c->prm.cut > 0 || c->prm.rgbmax > 0;
 }
 
+hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s) {
+    if (!c->cull) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_boxes, dim3((c->n_tiles + 3) / 4), dim3(256), 0, s, c->tiles, c->n_tiles,
+                       c->atom_off, c->n_atoms, xyz, c->tile_box, c->cull_count);
+    // the tile boxes' FP32 bounds are exact (min / max of the stored
+    // coordinates); the margin covers the rounding of the kernels' own r^2
+    const double rc[2] = {c->prm.rgbmax * (1.0 + 1e-5) + 1e-4, c->prm.cut * (1.0 + 1e-5) + 1e-4};
+    bool done[4][2] = {};
+    const int use[3] = {c->ni_born, c->ni_energy, c->ni_chain};
+    const int kind[3] = {0, 1, 0};
+    for (int k = 0; k < 3; ++k) {
+        const int idx = use[k] == 1 ? 0 : use[k] == 2 ? 1 : use[k] == 4 ? 2 : 3;
+        if (done[idx][kind[k]]) continue;
+        done[idx][kind[k]] = true;
+        const PairList& L = c->lists[idx];
+        if (L.n_items == 0) continue;
+        hipLaunchKernelGGL(k_cull, dim3((L.n_items + 255) / 256), dim3(256), 0, s, L.items, L.n_items, L.ni,
+                           c->atom_off, c->tile_base, c->tile_box, (float)(rc[kind[k]] * rc[kind[k]]),
+                           L.culled[kind[k]], L.n_culled[kind[k]]);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho,
                             const float* screen, hipStream_t s, LaunchEvents ev)
 {
     const PairList& L = list_for(c, c->ni_born);
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
+    const int2* items = c->cull ? L.culled[0] : L.items;
+    const int32_t* n_dev = c->cull ? L.n_culled[0] : nullptr;
     const float off = (float)c->prm.offset;
     const PairExt pe = make_pair_ext(c->prm);
     const bool ext = uses_ext(c);
 #define GBR_BORN(NI, EX) hipExtLaunchKernelGGL((k_born_pair<NI, EX>), grid, block, 0, s, ev.start, ev.stop, 0, \
-        L.items, L.n_items, c->atom_off, c->n_atoms, xyz, rho, screen, off, pe, c->psi_fx, c->err)
+        items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, off, pe, c->psi_fx, c->err)
     switch (L.ni) {
         case 1: if (ext) GBR_BORN(1, true); else GBR_BORN(1, false); break;
         case 2: if (ext) GBR_BORN(2, true); else GBR_BORN(2, false); break;
@@ -707,11 +812,13 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     const PairList& L = list_for(c, c->ni_energy);
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
+    const int2* items = c->cull ? L.culled[1] : L.items;
+    const int32_t* n_dev = c->cull ? L.n_culled[1] : nullptr;
     const float sq = (float)sqrt(c->prm.k_e / c->prm.eps_in);
     const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
     const PairExt pe = make_pair_ext(c->prm);
 #define GBR_EN(NI, GQ, EX) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ, EX>), grid, block, 0, s, ev.start, \
-        ev.stop, 0, L.items, L.n_items, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, pe, \
+        ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, pe, \
         force_fx, c->dEdR_fx, energy_fx, dEdq_fx, c->err)
 #define GBR_EN2(NI, GQ) if (uses_ext(c)) GBR_EN(NI, GQ, true); else GBR_EN(NI, GQ, false)
     const bool gq = dEdq_fx != nullptr;
@@ -733,10 +840,12 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
     const PairList& L = list_for(c, c->ni_chain);
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
+    const int2* items = c->cull ? L.culled[0] : L.items;
+    const int32_t* n_dev = c->cull ? L.n_culled[0] : nullptr;
     const float off = (float)c->prm.offset;
     const PairExt pe = make_pair_ext(c->prm);
 #define GBR_CH(NI, RH, EX) hipExtLaunchKernelGGL((k_chain_pair<NI, RH, EX>), grid, block, 0, s, ev.start, \
-        ev.stop, 0, L.items, L.n_items, c->atom_off, c->n_atoms, xyz, rho, screen, c->chain_c, off, pe, \
+        ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, c->chain_c, off, pe, \
         force_fx, dEdrho_fx, c->err)
 #define GBR_CH2(NI, RH) if (uses_ext(c)) GBR_CH(NI, RH, true); else GBR_CH(NI, RH, false)
     const bool rh = dEdrho_fx != nullptr;

@@ -54,8 +54,9 @@ def _lin(a, b, n):
     return tuple(float(v) for v in np.linspace(a, b, n))
 
 
-# The five workloads: a single-replica correctness system, the 2-D E,pH and
-# 3-D E,T,pH replica grids, a differentiation batch and an uneven batch.
+# The workloads: a single-replica correctness system, the 2-D E,pH and 3-D
+# E,T,pH replica grids, a differentiation batch, an uneven batch, and one large
+# system with salt and cutoffs.
 CONFIGS = {
     0: Workload("c0_single_256", (256,), 1, 1, 1, 1, (-0.2,), (6.5,), (300.0,), (DIM_E,),
                 1000, 10, 0, False, 1000, 2000),
@@ -68,6 +69,11 @@ CONFIGS = {
                 0, 10, 0, True, 1003, 2003),
     4: Workload("c4_uneven_64sys", (500, 20000), 4, 64, -1, -1, (-0.2,), (5.0, 6.0, 7.0, 8.0),
                 (300.0,), (DIM_PH,), 0, 10, 100, False, 1004, 2004),
+    # beyond the all-pairs regime: salt and cutoffs on one large system whose
+    # atoms come in compact 64-atom blocks (the pair passes cull distant tiles)
+    5: Workload("c5_salt_cutoff_1x100k", (100000,), 1, 1, -1, -1, (-0.2,), (7.0,), (300.0,), (DIM_E,),
+                0, 10, 0, False, 1005, 2005,
+                extra={"kappa": 0.1, "cut": 12.0, "rgbmax": 15.0, "blocked": True}),
 }
 
 PH_SITE_ATOMS = 4       # atoms per pH site; protonation adds 1/4 e to each
@@ -82,17 +88,25 @@ PKA_REF = 6.5
 E0_REF = -0.2           # V
 
 
-def lattice_sites(n_atoms: int, spacing: float = LATTICE):
-    """First n_atoms sites of an n^3 cubic lattice (n = ceil(cbrt N)), x fastest."""
+def lattice_sites(n_atoms: int, spacing: float = LATTICE, blocked: bool = False):
+    """First n_atoms sites of an n^3 cubic lattice (n = ceil(cbrt N)), x fastest;
+    with ``blocked`` the sites are ordered by 4 x 4 x 4 blocks first (blocks x
+    fastest, then within a block x fastest), so that 64 consecutive atoms fill
+    one compact cube."""
     n = 1
     while n ** 3 < n_atoms:
         n += 1
-    m = np.arange(n_atoms)
+    m = np.arange(n ** 3 if blocked else n_atoms)
     ijk = np.stack([m % n, (m // n) % n, m // (n * n)], axis=1)
+    if blocked:
+        nb = (n + 3) // 4
+        b, w = ijk // 4, ijk % 4
+        key = ((b[:, 2] * nb + b[:, 1]) * nb + b[:, 0]) * 64 + (w[:, 2] * 4 + w[:, 1]) * 4 + w[:, 0]
+        ijk = ijk[np.argsort(key, kind="stable")][:n_atoms]
     return ijk, ijk.astype(np.float64) * spacing
 
 
-def draw_system(n_atoms: int, seed: int, n_ph: int, n_redox: int, alternate=False):
+def draw_system(n_atoms: int, seed: int, n_ph: int, n_redox: int, alternate=False, blocked=False):
     """One system: jittered lattice, per-atom parameters and site clusters.
 
     Sites are disjoint clusters: for each site a random unused atom is drawn and
@@ -101,7 +115,7 @@ def draw_system(n_atoms: int, seed: int, n_ph: int, n_redox: int, alternate=Fals
     alternate pH, redox, pH, ... (n_ph + n_redox sites in total); otherwise all
     pH sites come first."""
     rng = np.random.default_rng(seed)
-    ijk, x0 = lattice_sites(n_atoms)
+    ijk, x0 = lattice_sites(n_atoms, blocked=blocked)
     xyz = x0 + rng.uniform(-JITTER, JITTER, size=x0.shape)
     q = rng.normal(0.0, 0.3, size=n_atoms)
     q -= q.mean()
@@ -215,7 +229,7 @@ def assemble(systems: list, reps_per_system: int, E_vals, pH_vals, T_vals, dim_o
 def make_config(idx: int, *, n_atoms: int | None = None, n_rep: int | None = None,
                 n_systems: int | None = None, per_replica_jitter: bool | None = None,
                 seed: int | None = None):
-    """Synthetic batch for workload ``idx`` (0..4); the keyword arguments
+    """Synthetic batch for workload ``idx`` (0..5); the keyword arguments
     shrink it for tests (fewer atoms, replicas or systems) while keeping the
     workload's structure and distributions."""
     w = CONFIGS[idx]
@@ -238,7 +252,12 @@ def make_config(idx: int, *, n_atoms: int | None = None, n_rep: int | None = Non
         return assemble(systems, w.replicas_per_system, w.E_vals, w.pH_vals, w.T_vals, w.dim_order,
                         **md)
     n = n_atoms or w.n_atoms[0]
-    base = draw_system(n, seed, w.n_ph, w.n_redox)
+    if w.n_ph < 0:                      # one site per 200 atoms, alternating pH / redox
+        ns = max(1, int(round(n / 200)))
+        base = draw_system(n, seed, (ns + 1) // 2, ns // 2, alternate=True,
+                           blocked=w.extra.get("blocked", False))
+    else:
+        base = draw_system(n, seed, w.n_ph, w.n_redox, blocked=w.extra.get("blocked", False))
     G = len(w.E_vals) * len(w.pH_vals) * len(w.T_vals)
     total = w.replicas_per_system * w.n_systems
     if n_rep is not None:

@@ -138,3 +138,27 @@ def test_full_size_uneven_batch_sampled_and_deterministic():
     # replicas of one system share coordinates: identical energies across its 4 replicas
     E = g1["E"][:, 4].reshape(-1, 4)
     assert np.all(E == E[:, :1])
+
+
+def test_blocked_20k_system_with_salt_and_culled_cutoffs_matches_oracle():
+    """One 20,000-atom system in compact 64-atom blocks with salt and both
+    cutoffs, so that the pair passes run culled work lists: energies, Born
+    radii and forces against the oracle.  The atoms sit exactly on the 3.0 A
+    lattice (no jitter), so every pair distance squared is a multiple of 9 A^2
+    and cut = 12.1 A, rgbmax = 15.1 A lie far from any of them (no pair sits
+    within FP32 rounding of a cutoff)."""
+    import paper_1809_07726_amd._capi as A
+    b = synth.make_config(5, n_atoms=20000)
+    b["xyz"] = b["x0"].copy()
+    P = A.obc2(kappa=0.1, cut=12.1, rgbmax=15.1)
+    G = oracle.obc2(kappa=0.1, cut=12.1, rgbmax=15.1)
+    g = gpu_eval(b, params=P)
+    n = 20000
+    Eo, gx, _, _ = oracle.gradient(b["xyz"], b["q"], b["rho"], b["screen"], b["sigma"], b["eps"], G)
+    _, Ro, _ = oracle.born(b["xyz"], b["rho"], b["screen"], G)
+    assert np.abs(g["R"] / Ro - 1).max() < 2e-6
+    assert abs(g["E"][0, 4] - Eo.sum()) <= E_TOL * abs(Eo.sum())
+    assert abs(g["E"][0, 0] - Eo[0]) <= E_TOL * abs(Eo[0])
+    assert rms_rel(g["F"], -gx) < F_TOL
+    _any_size_properties(b, g)
+    assert n == b["atom_off"][-1]
