@@ -62,12 +62,18 @@ def parse():
     return p.parse_args()
 
 
+# The files that hold the pair kernels' device code: the kernels, the device
+# helpers, the far-field fits and the work-list layout.
+PAIR_SOURCES = ("pair_kernels.hip", "gbr_device.h", "hct_poly.h", "pair_list.h")
+
+
 def source_hash():
+    """Hash of the pair kernels' sources, to tell whether a stored counter
+    profile was taken on the current pair kernels."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1809_07726_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in PAIR_SOURCES:
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -83,15 +83,6 @@ struct GBConstH {
 };
 GBConstH make_const(const gbr_gb_params& p);
 
-// Salt screening and pair cutoffs as the pair kernels use them (the EXT
-// variants; with kappa = 0 and no cutoffs the plain variants run):
-// kl2e = kappa log2(e), a = eps_in / eps_out, ak = a kappa, cut2 = cut^2 and
-// rgb2 = rgbmax^2 (FLT_MAX when off).
-struct PairExt {
-    float kl2e, a, ak, cut2, rgb2;
-};
-PairExt make_pair_ext(const gbr_gb_params& p);
-
 // kernel launchers (pair kernels) ----------------------------------------
 // ev: timing events (start, stop) recorded by the kernel's own dispatch
 // (hipExtLaunchKernel), or null.

@@ -39,6 +39,14 @@
 
 using namespace gbr;
 
+// Salt screening and pair cutoffs as the pair kernels use them (the EXT
+// variants; with kappa = 0 and no cutoffs the plain variants run):
+// kl2e = kappa log2(e), a = eps_in / eps_out, ak = a kappa, cut2 = cut^2 and
+// rgb2 = rgbmax^2 (FLT_MAX when off).
+struct PairExt {
+    float kl2e, a, ak, cut2, rgb2;
+};
+
 namespace {
 
 constexpr int MAXW = 4;                 // wavefronts per workgroup
@@ -744,7 +752,7 @@ const PairList& list_for(const gbr_ctx* c, int ni) {
 
 namespace gbr {
 
-PairExt make_pair_ext(const gbr_gb_params& p) {
+static PairExt make_pair_ext(const gbr_gb_params& p) {
     PairExt e;
     e.kl2e = (float)(p.kappa * 1.4426950408889634);
     e.a = (float)(p.eps_in / p.eps_out);
