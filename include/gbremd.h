@@ -84,6 +84,8 @@ extern "C" {
 #define GBR_DIM_E   0
 #define GBR_DIM_PH  1
 #define GBR_DIM_T   2
+#define GBR_DIM_H   3   /* Hamiltonian: scale of the GB + Coulomb + LJ energy */
+#define GBR_N_DIMS  4
 
 /* timed kernel kinds (gbr_get_timing) */
 #define GBR_K_BORN_PAIR   0   /* descreening pair pass                        */
@@ -137,16 +139,22 @@ typedef struct {
     const double*  ref_value;    /* [n_sites] pKa_ref (pH site) or E0_ref in V (redox)  */
 } gbr_sites;
 
-/* Replica grid: n_inst independent grids of nE x npH x nT target points;
- * grid point g = (iE * npH + ipH) * nT + iT; replicas sharing a grid instance
- * exchange targets.  Value tables are device pointers. */
+/* Replica grid: n_inst independent grids of nE x npH x nT x nHam target
+ * points; grid point g = ((iE * npH + ipH) * nT + iT) * nHam + iH; replicas
+ * sharing a grid instance exchange targets.  Value tables are device
+ * pointers.  The Hamiltonian dimension (Theory: multidimensional REMD may
+ * combine H-REMD with the others) is a family of potentials
+ *   U_l(x) = l (E_GB + E_C + E_LJ)(x) + E_tether(x)
+ * with one scale l = H_scale[iH] per level; nHam = 1 with H_scale NULL
+ * means l = 1 for every replica. */
 typedef struct {
-    int32_t n_inst, nE, npH, nT;
+    int32_t n_inst, nE, npH, nT, nHam;
     const double* E_vals;     /* [nE]  V  */
     const double* pH_vals;    /* [npH]    */
     const double* T_vals;     /* [nT]  K  */
-    int32_t n_dims;           /* 1..3: dimensions cycled by exchange attempts */
-    int32_t dim_order[3];     /* GBR_DIM_* in attempt order                   */
+    const double* H_scale;    /* [nHam] > 0, or NULL when nHam = 1 */
+    int32_t n_dims;           /* 1..4: dimensions cycled by exchange attempts */
+    int32_t dim_order[4];     /* GBR_DIM_* in attempt order                   */
 } gbr_grid;
 
 /* ------------------------------------------------------------------ context */
@@ -242,23 +250,26 @@ int titration_delta_e(gbr_ctx* ctx, const float* xyz, const float* q, const floa
                       const gbr_sites* sites, const int32_t* cand, int32_t n_cand,
                       double* dE, hipStream_t stream);
 
-/* One replica-exchange attempt (eqs. 3-5).  Attempt index a selects the
- * dimension dim_order[a % n_dims] and the parity (a / n_dims) % 2; grid points
- * k and k+1 along that dimension (k of that parity) are paired within every
- * line of equal other targets.  Log acceptance:
+/* One replica-exchange attempt (eqs. 3-5, and the Hamiltonian exchange of
+ * H-REMD).  Attempt index a selects the dimension dim_order[a % n_dims] and
+ * the parity (a / n_dims) % 2; grid points k and k+1 along that dimension (k
+ * of that parity) are paired within every line of equal other targets;
+ * replica i holds point k, j point k+1.  Log acceptance:
  *   pH: ln10 (pH_k - pH_k+1)(N_H,i - N_H,j)
  *   E : F/(kB T) (E_k - E_k+1)(N_e,i - N_e,j)
  *   T : (1/(kB T_k) - 1/(kB T_k+1)) (epsT_i - epsT_j)
+ *   H : (l_k - l_k+1)/(kB T) (enb_i - enb_j),  T, E, pH those of the line
  * accepted iff >= 0 or u < exp(.), u from Philox4x32-10(seed; ctr = {0, global
  * lower grid point, a, 4 << 24}).  Accepted pairs swap their target index and
  * grid_rep entries.  vscale [n_rep] receives sqrt(T_new / T_old) for replicas
  * whose temperature changed and 1 otherwise (the caller scales velocities).
- * In: nH, ne [n_rep] int32; epsT [n_rep] double.  In/out: target_idx
- * [3 n_rep] (iE, ipH, iT), grid_rep [n_inst * G].  ex_stats (may be NULL):
- * [2 * 3 * n_inst * G] uint32 attempts then accepts, indexed dim * n_inst G +
- * global lower grid point. */
+ * In: nH, ne [n_rep] int32; epsT [n_rep] double; enb [n_rep] double, the
+ * unscaled E_GB + E_C + E_LJ (read by H attempts only; may be NULL when the
+ * grid has nHam = 1).  In/out: target_idx [4 n_rep] (iE, ipH, iT, iH), grid_rep
+ * [n_inst * G].  ex_stats (may be NULL): [2 * 4 * n_inst * G] uint32 attempts
+ * then accepts, indexed dim * n_inst G + global lower grid point. */
 int remd_exchange(gbr_ctx* ctx, const gbr_grid* grid, uint64_t attempt,
-                  const int32_t* nH, const int32_t* ne, const double* epsT,
+                  const int32_t* nH, const int32_t* ne, const double* epsT, const double* enb,
                   int32_t* target_idx, int32_t* grid_rep, float* vscale,
                   uint32_t* ex_stats, uint64_t seed, hipStream_t stream);
 
@@ -267,12 +278,12 @@ typedef struct {
     float*    xyz;         /* [3N] positions, in/out                               */
     float*    v;           /* [3N] velocities A/ps, in/out                         */
     float*    q;           /* [N] charges, in/out (titration updates site atoms)   */
-    int64_t*  force_fx;    /* [3N] forces at xyz incl. tether, in/out (2^40)       */
-    int64_t*  energy_fx;   /* [4 n_rep] GB, C, LJ, tether at xyz, out (2^32)       */
+    int64_t*  force_fx;    /* [3N] forces of U_l at xyz, in/out (2^40)             */
+    int64_t*  energy_fx;   /* [4 n_rep] GB, C, LJ (unscaled), tether at xyz (2^32) */
     float*    R;           /* [N] Born radii at xyz, out                           */
     float*    dRdpsi;      /* [N] out                                               */
     int32_t*  site_state;  /* [n_sites] in/out                                      */
-    int32_t*  target_idx;  /* [3 n_rep] in/out                                     */
+    int32_t*  target_idx;  /* [4 n_rep] in/out                                     */
     int32_t*  grid_rep;    /* [n_inst G] in/out                                    */
     double*   ke;          /* [n_rep] kinetic energy after the step, may be NULL   */
     uint32_t* mc_stats;    /* [2 n_sites] attempts then accepts, may be NULL       */
@@ -302,11 +313,12 @@ typedef struct {
  * T[iT], Philox normals), A; if (n+1) % mc_every == 0: Born radii at the new
  * positions, one protonation attempt then one redox attempt per replica
  * (uniformly chosen site of that type, uniformly chosen other state,
- * Metropolis on dE - dG_ref + kT ln10 (pH - pKa_ref) dN_H or
- * + F (E - E0_ref) dN_e); forces at the new positions (GB + C + LJ + tether
- * k |x - x0|^2); B; then if (n+1) % ex_every == 0 exchange attempt
- * (n+1)/ex_every - 1 with epsT = U - sum G_ref + sum_redox F (E - E0_ref) N_e
- * (eps_mode 0) or U (eps_mode 1), and velocities scaled after T swaps.
+ * Metropolis on l dE - dG_ref + kT ln10 (pH - pKa_ref) dN_H or
+ * + F (E - E0_ref) dN_e); forces of U_l = l (GB + C + LJ) + tether
+ * k |x - x0|^2 at the new positions, l the replica's Hamiltonian scale; B;
+ * then if (n+1) % ex_every == 0 exchange attempt (n+1)/ex_every - 1 with
+ * epsT = U_l - sum G_ref + sum_redox F (E - E0_ref) N_e (eps_mode 0) or U_l
+ * (eps_mode 1), and velocities scaled after T swaps.
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = {seed low 32,
  * seed high 32}, counter = {sub, entity, step low 32, stream << 24 | step bits
  * 32..55}: stream 1 = O-step noise (entity = replica, sub = 2 * local atom + 0/1,
@@ -335,10 +347,11 @@ int gbr_fx_to_float(gbr_ctx* ctx, const int64_t* src, int32_t components, int32_
  * out[5 r + 4] = E_GB + E_C + E_LJ of replica r. */
 int gbr_energies(gbr_ctx* ctx, const int64_t* energy_fx, double* out, hipStream_t stream);
 
-/* Per-replica exchange inputs from the current state: protons, electrons and
- * the T-exchange energy (as md_step computes them). */
+/* Per-replica exchange inputs from the current state: protons, electrons,
+ * the T-exchange energy and the unscaled E_GB + E_C + E_LJ (as md_step
+ * computes them; enb may be NULL). */
 int gbr_exchange_inputs(gbr_ctx* ctx, const gbr_md_state* state, const gbr_md_params* params,
-                        int32_t* nH, int32_t* ne, double* epsT, hipStream_t stream);
+                        int32_t* nH, int32_t* ne, double* epsT, double* enb, hipStream_t stream);
 
 #ifdef __cplusplus
 }

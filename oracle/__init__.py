@@ -75,9 +75,10 @@ class MDCfg(C.Structure):
         ("site_type", _P(C.c_int)), ("n_states", _P(C.c_int)),
         ("state_q", _P(C.c_double)), ("state_nH", _P(C.c_int)), ("state_ne", _P(C.c_int)),
         ("G_ref", _P(C.c_double)), ("ref_value", _P(C.c_double)),
-        ("n_inst", C.c_int), ("nE", C.c_int), ("npH", C.c_int), ("nT", C.c_int),
+        ("n_inst", C.c_int), ("nE", C.c_int), ("npH", C.c_int), ("nT", C.c_int), ("nHam", C.c_int),
         ("E_vals", _P(C.c_double)), ("pH_vals", _P(C.c_double)), ("T_vals", _P(C.c_double)),
-        ("n_dims", C.c_int), ("dim_order", C.c_int * 3),
+        ("H_scale", _P(C.c_double)),
+        ("n_dims", C.c_int), ("dim_order", C.c_int * 4),
         ("rho", _P(C.c_double)), ("scr", _P(C.c_double)), ("sig", _P(C.c_double)),
         ("eps", _P(C.c_double)), ("mass", _P(C.c_double)), ("x0", _P(C.c_double)),
         ("gb", GBParams),
@@ -119,7 +120,7 @@ def _declare(L):
     L.orc_tether.restype = C.c_double
     L.orc_md_run.argtypes = [_P(MDCfg), _P(MDState), C.c_longlong, C.c_int, C.c_int]
     L.orc_md_run.restype = C.c_int
-    L.orc_exchange.argtypes = [_P(MDCfg), C.c_longlong, _ip, _ip, _dp, _ip, _ip, _dp,
+    L.orc_exchange.argtypes = [_P(MDCfg), C.c_longlong, _ip, _ip, _dp, _dp, _ip, _ip, _dp,
                                _P(C.c_longlong), _P(C.c_longlong)]
     L.orc_replica_counts.argtypes = [_P(MDCfg), _ip, _ip, _dp, C.c_int,
                                      _P(C.c_int), _P(C.c_int), _P(C.c_double)]
@@ -291,13 +292,16 @@ def make_md(sysd: dict, gb=None, seed=0, eps_mode=0):
         setattr(cfg, name, _ptr(i(sysd[name]), C.c_int))
     for name in ("state_q", "G_ref", "ref_value"):
         setattr(cfg, name, _ptr(f(sysd[name]), C.c_double))
-    cfg.n_inst, cfg.nE, cfg.npH, cfg.nT = (int(sysd["n_inst"]), len(sysd["E_vals"]),
-                                           len(sysd["pH_vals"]), len(sysd["T_vals"]))
+    H_scale = np.asarray(sysd.get("H_scale", [1.0]), np.float64)
+    cfg.n_inst, cfg.nE, cfg.npH, cfg.nT, cfg.nHam = (int(sysd["n_inst"]), len(sysd["E_vals"]),
+                                                     len(sysd["pH_vals"]), len(sysd["T_vals"]),
+                                                     H_scale.size)
     for name in ("E_vals", "pH_vals", "T_vals"):
         setattr(cfg, name, _ptr(f(sysd[name]), C.c_double))
+    cfg.H_scale = _ptr(f(H_scale), C.c_double)
     order = list(sysd["dim_order"])
     cfg.n_dims = len(order)
-    for k in range(3):
+    for k in range(4):
         cfg.dim_order[k] = order[k] if k < len(order) else 0
     for name, key in (("rho", "rho"), ("scr", "screen"), ("sig", "sigma"), ("eps", "eps"),
                       ("mass", "mass")):
@@ -324,8 +328,8 @@ def make_md(sysd: dict, gb=None, seed=0, eps_mode=0):
         "target_idx": i(np.asarray(sysd["target_idx"]).reshape(-1)),
         "grid_rep": i(sysd["grid_rep"]),
         "mc_att": ll(cfg.n_sites), "mc_acc": ll(cfg.n_sites),
-        "ex_att": ll(3 * cfg.n_inst * cfg.nE * cfg.npH * cfg.nT),
-        "ex_acc": ll(3 * cfg.n_inst * cfg.nE * cfg.npH * cfg.nT),
+        "ex_att": ll(4 * cfg.n_rep),
+        "ex_acc": ll(4 * cfg.n_rep),
     }
     for k, a in arrs.items():
         ct = C.c_double if a.dtype == np.float64 else (C.c_int if a.dtype == np.int32 else C.c_longlong)
@@ -348,14 +352,16 @@ def replica_counts(cfg, site_state, target_idx, E4):
     return nH, ne, ep
 
 
-def exchange(cfg, attempt, nH, ne, epsT, target_idx, grid_rep):
-    """One exchange attempt; returns (target_idx, grid_rep, vscale, att, acc)."""
+def exchange(cfg, attempt, nH, ne, epsT, target_idx, grid_rep, E4=None):
+    """One exchange attempt; E4 [n_rep, 4] (GB, Coulomb, LJ, tether) is read by
+    Hamiltonian attempts.  Returns (target_idx, grid_rep, vscale, att, acc)."""
     ti = _i32(np.asarray(target_idx).reshape(-1)).copy()
     gr = _i32(grid_rep).copy()
     vs = np.ones(cfg.n_rep)
-    GT = cfg.n_inst * cfg.nE * cfg.npH * cfg.nT
-    att = np.zeros(3 * GT, dtype=np.int64)
-    acc = np.zeros(3 * GT, dtype=np.int64)
-    lib().orc_exchange(C.byref(cfg), int(attempt), _i32(nH), _i32(ne), _f64(epsT), ti, gr, vs,
+    GT = cfg.n_inst * cfg.nE * cfg.npH * cfg.nT * cfg.nHam
+    att = np.zeros(4 * GT, dtype=np.int64)
+    acc = np.zeros(4 * GT, dtype=np.int64)
+    e4 = _f64(np.zeros((cfg.n_rep, 4)) if E4 is None else E4).reshape(-1)
+    lib().orc_exchange(C.byref(cfg), int(attempt), _i32(nH), _i32(ne), _f64(epsT), e4, ti, gr, vs,
                        att.ctypes.data_as(_P(C.c_longlong)), acc.ctypes.data_as(_P(C.c_longlong)))
-    return ti.reshape(-1, 3), gr, vs, att, acc
+    return ti.reshape(-1, 4), gr, vs, att, acc

@@ -20,6 +20,10 @@
  *   - Replica exchange: eq. 3 (pH), eq. 4 (E), eq. 5 (T); one dimension per
  *     attempt, cycled in a user order, nearest neighbours only, among replicas
  *     sharing the other targets (Theory: AMBER's multidimensional REMD module).
+ *     A fourth, Hamiltonian dimension (H-REMD, which the same module may
+ *     combine with the others) holds a family of potentials U_l = l (E_GB +
+ *     E_C + E_LJ) + E_tether; its exchanges use the Metropolis rule for two
+ *     replicas trading Hamiltonians at one temperature.
  *   - Dynamics: Langevin (Calculation details) integrated with the BAOAB
  *     splitting of Leimkuhler and Matthews.
  *   - Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
@@ -41,7 +45,7 @@
 #define ORC_TWO_PI 6.283185307179586477
 
 enum { ORC_STREAM_O = 1, ORC_STREAM_MCPH = 2, ORC_STREAM_MCRED = 3, ORC_STREAM_EX = 4 };
-enum { ORC_DIM_E = 0, ORC_DIM_PH = 1, ORC_DIM_T = 2 };
+enum { ORC_DIM_E = 0, ORC_DIM_PH = 1, ORC_DIM_T = 2, ORC_DIM_H = 3, ORC_NDIM = 4 };
 
 typedef struct {
     double k_e;      /* Coulomb constant, kcal A / (mol e^2)             */
@@ -501,11 +505,12 @@ typedef struct {
     const int* state_ne;
     const double* G_ref;       /* [site * max_states + state], kcal/mol */
     const double* ref_value;   /* pKa_ref (pH sites) or E0_ref in V (redox sites) */
-    /* replica grid: n_inst independent grids of nE x npH x nT points,
-     * grid point g = (iE * npH + ipH) * nT + iT */
-    int n_inst, nE, npH, nT;
-    const double* E_vals; const double* pH_vals; const double* T_vals;
-    int n_dims; int dim_order[3];
+    /* replica grid: n_inst independent grids of nE x npH x nT x nHam points,
+     * grid point g = ((iE * npH + ipH) * nT + iT) * nHam + iH; H_scale[iH] is
+     * the scale l of the GB + Coulomb + LJ energy at Hamiltonian level iH */
+    int n_inst, nE, npH, nT, nHam;
+    const double* E_vals; const double* pH_vals; const double* T_vals; const double* H_scale;
+    int n_dims; int dim_order[4];
     /* per-atom parameters */
     const double* rho; const double* scr; const double* sig; const double* eps;
     const double* mass; const double* x0;
@@ -519,17 +524,25 @@ typedef struct {
     double* xyz;            /* AoS [3 Ntot] */
     double* v;              /* AoS [3 Ntot] */
     double* q;              /* [Ntot] */
-    double* F;              /* AoS [3 Ntot], forces at xyz (including the tether) */
-    double* E;              /* [n_rep * 4]: GB, Coulomb, LJ, tether at xyz */
+    double* F;              /* AoS [3 Ntot], forces of U_l at xyz (tether included) */
+    double* E;              /* [n_rep * 4]: GB, Coulomb, LJ (unscaled), tether at xyz */
     int* site_state;        /* [n_sites] */
-    int* target_idx;        /* [n_rep * 3]: iE, ipH, iT */
-    int* grid_rep;          /* [n_inst * nE * npH * nT] */
+    int* target_idx;        /* [n_rep * 4]: iE, ipH, iT, iH */
+    int* grid_rep;          /* [n_inst * nE * npH * nT * nHam] */
     long long* mc_att;      /* [n_sites] */
     long long* mc_acc;
-    long long* ex_att;      /* [3 * n_inst * G], indexed dim * (n_inst G) + global lower point */
+    long long* ex_att;      /* [4 * n_inst * G], indexed dim * (n_inst G) + global lower point */
     long long* ex_acc;
 } orc_md_state;
 
+/* Scale l of replica r's GB + Coulomb + LJ energy (its Hamiltonian level). */
+static double orc_lambda(const orc_md_cfg* c, const int* target_idx, int r)
+{
+    return c->H_scale ? c->H_scale[target_idx[ORC_NDIM * r + ORC_DIM_H]] : 1.0;
+}
+
+/* Forces of U_l = l (E_GB + E_C + E_LJ) + E_tether for replica r at its
+ * positions; the energy components are stored unscaled. */
 static void orc_forces_one(const orc_md_cfg* c, orc_md_state* s, int r)
 {
     int a0 = c->atom_off[r], n = c->atom_off[r + 1] - a0;
@@ -537,6 +550,8 @@ static void orc_forces_one(const orc_md_cfg* c, orc_md_state* s, int r)
     double E3[3];
     orc_gradient(n, s->xyz + 3 * a0, s->q + a0, c->rho + a0, c->scr + a0, c->sig + a0, c->eps + a0,
                  &c->gb, E3, g, NULL, NULL);
+    double lam = orc_lambda(c, s->target_idx, r);
+    for (int i = 0; i < 3 * n; ++i) g[i] *= lam;
     double et = orc_tether(n, s->xyz + 3 * a0, c->x0 + 3 * a0, c->k_tether, g);
     for (int i = 0; i < 3 * n; ++i) s->F[3 * a0 + i] = -g[i];
     s->E[4 * r + 0] = E3[0]; s->E[4 * r + 1] = E3[1]; s->E[4 * r + 2] = E3[2]; s->E[4 * r + 3] = et;
@@ -544,9 +559,11 @@ static void orc_forces_one(const orc_md_cfg* c, orc_md_state* s, int r)
 }
 
 /* One Monte Carlo attempt on one site type for replica r (eqs. 1-2 weights):
- *   dG = dE_elec - [G_ref(s') - G_ref(s)] + kT ln10 (pH - pKa_ref) (N_H(s') - N_H(s))   (pH site)
- *   dG = dE_elec - [G_ref(s') - G_ref(s)] + F (E - E0_ref) (N_e(s') - N_e(s))           (redox site)
- * accepted iff dG <= 0 or u < exp(-dG / kT). Born radii are those of the current geometry. */
+ *   dG = l dE_elec - [G_ref(s') - G_ref(s)] + kT ln10 (pH - pKa_ref) (N_H(s') - N_H(s))   (pH site)
+ *   dG = l dE_elec - [G_ref(s') - G_ref(s)] + F (E - E0_ref) (N_e(s') - N_e(s))           (redox site)
+ * (l: the replica's Hamiltonian scale, which multiplies its electrostatic
+ * energy) accepted iff dG <= 0 or u < exp(-dG / kT). Born radii are those of
+ * the current geometry. */
 static void orc_mc_one(const orc_md_cfg* c, orc_md_state* s, int r, const double* R,
                        uint64_t step, int type)
 {
@@ -578,15 +595,15 @@ static void orc_mc_one(const orc_md_cfg* c, orc_md_state* s, int r, const double
         qn[k] = c->state_q[(size_t)slot * ms + nw];
     }
     double dE = orc_delta_e_plain(n, s->xyz + 3 * a0, s->q + a0, R, &c->gb, m, idx, qn);
-    double T = c->T_vals[s->target_idx[3 * r + 2]];
+    double T = c->T_vals[s->target_idx[ORC_NDIM * r + ORC_DIM_T]];
     double kT = ORC_KB * T;
-    double dG = dE - (c->G_ref[site * ms + nw] - c->G_ref[site * ms + cur]);
+    double dG = orc_lambda(c, s->target_idx, r) * dE - (c->G_ref[site * ms + nw] - c->G_ref[site * ms + cur]);
     if (type == 0) {
-        double pH = c->pH_vals[s->target_idx[3 * r + 1]];
+        double pH = c->pH_vals[s->target_idx[ORC_NDIM * r + ORC_DIM_PH]];
         dG += kT * ORC_LN10 * (pH - c->ref_value[site])
             * (double)(c->state_nH[site * ms + nw] - c->state_nH[site * ms + cur]);
     } else {
-        double Ev = c->E_vals[s->target_idx[3 * r + 0]];
+        double Ev = c->E_vals[s->target_idx[ORC_NDIM * r + ORC_DIM_E]];
         dG += ORC_FARAD * (Ev - c->ref_value[site])
             * (double)(c->state_ne[site * ms + nw] - c->state_ne[site * ms + cur]);
     }
@@ -603,15 +620,16 @@ static void orc_mc_one(const orc_md_cfg* c, orc_md_state* s, int r, const double
 /* Protons, electrons and the exchange energy of replica r.  eps_mode 0 is the
  * energy whose Boltzmann factor the titration moves sample at fixed pH and E:
  * U - sum G_ref(s) + sum_redox F (E - E0_ref) N_e(s)  (the pH term carries kT
- * and cancels in eq. 5); eps_mode 1 is the potential energy U alone. */
+ * and cancels in eq. 5); eps_mode 1 is the potential energy U alone.  U is
+ * the replica's own potential U_l = l (E_GB + E_C + E_LJ) + E_tether. */
 void orc_replica_counts(const orc_md_cfg* c, const int* site_state, const int* target_idx,
                         const double* E4, int r, int* nH, int* ne, double* epsT)
 {
     int ms = c->max_states;
     int h = 0, e = 0;
-    double U = E4[4 * r] + E4[4 * r + 1] + E4[4 * r + 2] + E4[4 * r + 3];
+    double U = orc_lambda(c, target_idx, r) * (E4[4 * r] + E4[4 * r + 1] + E4[4 * r + 2]) + E4[4 * r + 3];
     double extra = 0.0;
-    double Ev = c->E_vals[target_idx[3 * r + 0]];
+    double Ev = c->E_vals[target_idx[ORC_NDIM * r + ORC_DIM_E]];
     for (int k = c->rep_site_off[r]; k < c->rep_site_off[r + 1]; ++k) {
         int st = site_state[k];
         h += c->state_nH[k * ms + st];
@@ -624,30 +642,42 @@ void orc_replica_counts(const orc_md_cfg* c, const int* site_state, const int* t
     *epsT = c->eps_mode == 0 ? U + extra : U;
 }
 
+/* Potential energy of a configuration whose energy components (GB, Coulomb,
+ * LJ, tether) are E4[0..3], under the Hamiltonian of scale l. */
+static double orc_U(double l, const double* E4)
+{
+    return l * (E4[0] + E4[1] + E4[2]) + E4[3];
+}
+
 /* One exchange attempt (attempt index a): dimension dim_order[a % n_dims],
  * parity (a / n_dims) % 2; pairs of grid points (k, k+1) along that dimension
  * with k of that parity, within each line of equal other targets; acceptance
- * eq. 3, 4 or 5 against u drawn for the lower grid point.  On acceptance the
- * two replicas swap their target index in that dimension; a temperature swap
- * scales each replica's velocities by sqrt(T_new / T_old): the factor is
- * multiplied into vscale[replica] (vscale may be NULL). */
+ * eq. 3, 4 or 5 against u drawn for the lower grid point.  A Hamiltonian
+ * attempt between replica i (level k) and j (level k+1) at temperature T
+ * accepts with min(1, exp(-[U_k(x_j) + U_k+1(x_i) - U_k(x_i) - U_k+1(x_j)] / kT)),
+ * the energies formed from the replicas' components E4 [n_rep * 4].  On
+ * acceptance the two replicas swap their target index in that dimension; a
+ * temperature swap scales each replica's velocities by sqrt(T_new / T_old):
+ * the factor is multiplied into vscale[replica] (vscale may be NULL). */
 void orc_exchange(const orc_md_cfg* c, long long a, const int* nH, const int* ne, const double* epsT,
-                  int* target_idx, int* grid_rep, double* vscale, long long* ex_att, long long* ex_acc)
+                  const double* E4, int* target_idx, int* grid_rep, double* vscale,
+                  long long* ex_att, long long* ex_acc)
 {
     int d = c->dim_order[a % c->n_dims];
     int parity = (int)((a / c->n_dims) % 2);
-    int dimsz[3] = { c->nE, c->npH, c->nT };
-    int G = c->nE * c->npH * c->nT;
+    int dimsz[ORC_NDIM] = { c->nE, c->npH, c->nT, c->nHam };
+    int G = c->nE * c->npH * c->nT * c->nHam;
     int GT = G * c->n_inst;
     for (int inst = 0; inst < c->n_inst; ++inst) {
         for (int g = 0; g < G; ++g) {
-            int iE = g / (c->npH * c->nT), ipH = (g / c->nT) % c->npH, iT = g % c->nT;
-            int coord[3] = { iE, ipH, iT };
+            int iH = g % c->nHam, iT = (g / c->nHam) % c->nT;
+            int ipH = (g / (c->nHam * c->nT)) % c->npH, iE = g / (c->nHam * c->nT * c->npH);
+            int coord[ORC_NDIM] = { iE, ipH, iT, iH };
             int k = coord[d];
             if (k % 2 != parity || k + 1 >= dimsz[d]) continue;
-            int c2[3] = { iE, ipH, iT };
+            int c2[ORC_NDIM] = { iE, ipH, iT, iH };
             c2[d] = k + 1;
-            int g2 = (c2[0] * c->npH + c2[1]) * c->nT + c2[2];
+            int g2 = ((c2[0] * c->npH + c2[1]) * c->nT + c2[2]) * c->nHam + c2[3];
             int gl = inst * G + g, gu = inst * G + g2;
             int ri = grid_rep[gl], rj = grid_rep[gu];
             double delta;
@@ -656,17 +686,23 @@ void orc_exchange(const orc_md_cfg* c, long long a, const int* nH, const int* ne
             } else if (d == ORC_DIM_E) {
                 double kT = ORC_KB * c->T_vals[iT];
                 delta = ORC_FARAD / kT * (c->E_vals[k] - c->E_vals[k + 1]) * (double)(ne[ri] - ne[rj]);
-            } else {
+            } else if (d == ORC_DIM_T) {
                 double bi = 1.0 / (ORC_KB * c->T_vals[k]), bj = 1.0 / (ORC_KB * c->T_vals[k + 1]);
                 delta = (bi - bj) * (epsT[ri] - epsT[rj]);
+            } else {
+                double kT = ORC_KB * c->T_vals[iT];
+                double lk = c->H_scale[k], lk1 = c->H_scale[k + 1];
+                const double* Ei = E4 + 4 * ri;
+                const double* Ej = E4 + 4 * rj;
+                delta = -((orc_U(lk, Ej) + orc_U(lk1, Ei)) - (orc_U(lk, Ei) + orc_U(lk1, Ej))) / kT;
             }
             uint32_t w[4];
             orc_draw(c->seed, 0u, (uint32_t)gl, (uint64_t)a, ORC_STREAM_EX, w);
             double u = orc_uniform53(w[0], w[1]);
             if (ex_att) ex_att[(size_t)d * GT + gl] += 1;
             if (delta >= 0.0 || u < exp(delta)) {
-                target_idx[3 * ri + d] = k + 1;
-                target_idx[3 * rj + d] = k;
+                target_idx[ORC_NDIM * ri + d] = k + 1;
+                target_idx[ORC_NDIM * rj + d] = k;
                 grid_rep[gl] = rj; grid_rep[gu] = ri;
                 if (ex_acc) ex_acc[(size_t)d * GT + gl] += 1;
                 if (d == ORC_DIM_T && vscale) {
@@ -694,6 +730,7 @@ int orc_md_run(const orc_md_cfg* c, orc_md_state* s, long long step0, int n_step
     int* ne = (int*)malloc((size_t)c->n_rep * sizeof(int));
     double* epsT = (double*)malloc((size_t)c->n_rep * sizeof(double));
     double* vscale = (double*)malloc((size_t)c->n_rep * sizeof(double));
+    double* lam_old = (double*)malloc((size_t)c->n_rep * sizeof(double));
     double* R = (double*)malloc((size_t)ntot * sizeof(double));
     double c1 = exp(-c->gamma_ps * c->dt);
     double c2 = sqrt(1.0 - c1 * c1);
@@ -702,7 +739,7 @@ int orc_md_run(const orc_md_cfg* c, orc_md_state* s, long long step0, int n_step
         uint64_t n = (uint64_t)(step0 + st);
         for (int r = 0; r < c->n_rep; ++r) {
             int a0 = c->atom_off[r], na = c->atom_off[r + 1] - a0;
-            double kT = ORC_KB * c->T_vals[s->target_idx[3 * r + 2]];
+            double kT = ORC_KB * c->T_vals[s->target_idx[ORC_NDIM * r + ORC_DIM_T]];
             for (int i = 0; i < na; ++i) {
                 int a = a0 + i;
                 double im = ORC_CONV / c->mass[a];
@@ -739,16 +776,21 @@ int orc_md_run(const orc_md_cfg* c, orc_md_state* s, long long step0, int n_step
             for (int r = 0; r < c->n_rep; ++r) {
                 orc_replica_counts(c, s->site_state, s->target_idx, s->E, r, &nH[r], &ne[r], &epsT[r]);
                 vscale[r] = 1.0;
+                lam_old[r] = orc_lambda(c, s->target_idx, r);
             }
-            orc_exchange(c, att, nH, ne, epsT, s->target_idx, s->grid_rep, vscale, s->ex_att, s->ex_acc);
+            orc_exchange(c, att, nH, ne, epsT, s->E, s->target_idx, s->grid_rep, vscale,
+                         s->ex_att, s->ex_acc);
             for (int r = 0; r < c->n_rep; ++r) {
+                /* a replica given another Hamiltonian needs that Hamiltonian's
+                 * forces for the next half kick */
+                if (orc_lambda(c, s->target_idx, r) != lam_old[r]) orc_forces_one(c, s, r);
                 if (vscale[r] == 1.0) continue;
                 for (int a = c->atom_off[r]; a < c->atom_off[r + 1]; ++a)
                     for (int d = 0; d < 3; ++d) s->v[3 * a + d] *= vscale[r];
             }
         }
     }
-    free(nH); free(ne); free(epsT); free(vscale); free(R);
+    free(nH); free(ne); free(epsT); free(vscale); free(lam_old); free(R);
     return 0;
 }
 

@@ -20,7 +20,8 @@ ERR_NONFINITE, ERR_OVERFLOW, ERR_RADIUS, ERR_SITE = 1, 2, 4, 8
 FX_BITS_FORCE, FX_BITS_ENERGY = 40, 32
 GRAD_Q, GRAD_RHO, ZERO_OUT = 1, 2, 4
 MD_INIT_FORCES, MD_GRAPH = 1, 2
-DIM_E, DIM_PH, DIM_T = 0, 1, 2
+DIM_E, DIM_PH, DIM_T, DIM_H = 0, 1, 2, 3
+N_DIMS = 4
 K_BORN_PAIR, K_ENERGY_PAIR, K_CHAIN_PAIR, K_PER_ATOM, K_TITRATION, K_EXCHANGE, K_COUNT = range(7)
 KERNEL_KINDS = ("born_pair", "energy_pair", "chain_pair", "per_atom", "titration", "exchange")
 
@@ -56,8 +57,8 @@ class Sites(C.Structure):
 
 class Grid(C.Structure):
     _fields_ = [("n_inst", C.c_int32), ("nE", C.c_int32), ("npH", C.c_int32), ("nT", C.c_int32),
-                ("E_vals", _vp), ("pH_vals", _vp), ("T_vals", _vp),
-                ("n_dims", C.c_int32), ("dim_order", C.c_int32 * 3)]
+                ("nHam", C.c_int32), ("E_vals", _vp), ("pH_vals", _vp), ("T_vals", _vp),
+                ("H_scale", _vp), ("n_dims", C.c_int32), ("dim_order", C.c_int32 * 4)]
 
 
 class MDState(C.Structure):
@@ -91,11 +92,11 @@ def _load():
     L.gb_born_radii.argtypes = [_vp] + [_vp] * 6 + [_vp]
     L.gb_energy_forces.argtypes = [_vp] + [_vp] * 9 + [_vp, _vp, i32, _vp, _vp, _vp]
     L.titration_delta_e.argtypes = [_vp, _vp, _vp, _vp, P(Sites), _vp, i32, _vp, _vp]
-    L.remd_exchange.argtypes = [_vp, P(Grid), u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, u64, _vp]
+    L.remd_exchange.argtypes = [_vp, P(Grid), u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, u64, _vp]
     L.md_step.argtypes = [_vp, P(MDState), P(MDParams), u64, u64, i32, i32, _vp]
     L.gbr_fx_to_float.argtypes = [_vp, _vp, i32, i32, _vp, i32, _vp, _vp]
     L.gbr_energies.argtypes = [_vp, _vp, _vp, _vp]
-    L.gbr_exchange_inputs.argtypes = [_vp, P(MDState), P(MDParams), _vp, _vp, _vp, _vp]
+    L.gbr_exchange_inputs.argtypes = [_vp, P(MDState), P(MDParams), _vp, _vp, _vp, _vp, _vp]
     for name in EXPORTED:
         if name != "gbr_last_error":
             getattr(L, name).restype = C.c_int

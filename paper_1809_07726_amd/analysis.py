@@ -2,7 +2,7 @@
 
 Exchange diagnostics (what the paper reports about replica walks in its
 Results, "Temperature dependence ..." subsection and Fig. 7): per-replica
-residence histograms over the E x pH x T target grid and per-dimension
+residence histograms over the E x pH x T (x H) target grid and per-dimension
 acceptance from the on-device counters of md_step.
 
 Titration analysis (Theory, eqs. 1-2 and 6-8): protonated / reduced fractions
@@ -22,22 +22,23 @@ import numpy as np
 KB = 0.001987204259        # kcal/(mol K), CODATA 2018 R / 4184
 FARADAY = 23.0605480       # kcal/(mol V), CODATA 2018 F / 4184
 LN10 = math.log(10.0)
-DIMS = ("E", "pH", "T")
+DIMS = ("E", "pH", "T", "H")
 
 
 # ------------------------------------------------------------------ grid
-def grid_index(target_idx, npH: int, nT: int):
-    """Grid point g = (iE * npH + ipH) * nT + iT for target rows [.., 3]."""
+def grid_index(target_idx, npH: int, nT: int, nHam: int = 1):
+    """Grid point g = ((iE * npH + ipH) * nT + iT) * nHam + iH for target rows
+    [.., 4]."""
     t = np.asarray(target_idx)
-    return (t[..., 0] * npH + t[..., 1]) * nT + t[..., 2]
+    return ((t[..., 0] * npH + t[..., 1]) * nT + t[..., 2]) * nHam + t[..., 3]
 
 
-def residence_histogram(target_snapshots, nE: int, npH: int, nT: int):
+def residence_histogram(target_snapshots, nE: int, npH: int, nT: int, nHam: int = 1):
     """counts[r, g]: number of snapshots in which replica r sat at grid point g
-    (snapshots: [n_snap, n_rep, 3] target indices)."""
+    (snapshots: [n_snap, n_rep, 4] target indices)."""
     s = np.asarray(target_snapshots)
-    g = grid_index(s, npH, nT)                     # [n_snap, n_rep]
-    G = nE * npH * nT
+    g = grid_index(s, npH, nT, nHam)               # [n_snap, n_rep]
+    G = nE * npH * nT * nHam
     n_rep = s.shape[1]
     counts = np.zeros((n_rep, G), dtype=np.int64)
     for r in range(n_rep):
@@ -57,12 +58,12 @@ def walk_summary(counts, n_inst: int = 1):
             "worst_ratio": float(ratio.max())}
 
 
-def exchange_acceptance(ex_stats, n_inst: int, nE: int, npH: int, nT: int):
-    """From md_step's ex_stats counters ([attempts(3 G_tot), accepts(3 G_tot)],
+def exchange_acceptance(ex_stats, n_inst: int, nE: int, npH: int, nT: int, nHam: int = 1):
+    """From md_step's ex_stats counters ([attempts(4 G_tot), accepts(4 G_tot)],
     indexed dim * G_tot + global lower grid point): acceptance per dimension and
     per lower grid point."""
-    GT = n_inst * nE * npH * nT
-    st = np.asarray(ex_stats, dtype=np.int64).reshape(2, 3, GT)
+    GT = n_inst * nE * npH * nT * nHam
+    st = np.asarray(ex_stats, dtype=np.int64).reshape(2, len(DIMS), GT)
     att, acc = st[0], st[1]
     out = {}
     for d, name in enumerate(DIMS):
@@ -80,20 +81,20 @@ def mc_acceptance(mc_stats):
 
 # ------------------------------------------------------------ fractions
 def fractions_per_point(state_snapshots, target_snapshots, rep_site_off, nE, npH, nT,
-                        n_inst: int = 1):
+                        n_inst: int = 1, nHam: int = 1):
     """occ[g, k]: time-averaged state (0/1) of the k-th site of a replica over the
     snapshots in which that replica sat at grid point g (summed over grid
     instances, which share the topology), and n[g] the number of samples.
-    state_snapshots: [n_snap, n_sites]; target_snapshots: [n_snap, n_rep, 3]."""
+    state_snapshots: [n_snap, n_sites]; target_snapshots: [n_snap, n_rep, 4]."""
     S = np.asarray(state_snapshots)
     T = np.asarray(target_snapshots)
     off = np.asarray(rep_site_off)
     n_rep = off.size - 1
     k_sites = int(off[1] - off[0])
-    G = nE * npH * nT
+    G = nE * npH * nT * nHam
     tot = np.zeros((G, k_sites))
     n = np.zeros(G)
-    g = grid_index(T, npH, nT)
+    g = grid_index(T, npH, nT, nHam)
     for r in range(n_rep):
         st = S[:, off[r]:off[r + 1]]
         np.add.at(tot, g[:, r], st)

@@ -104,15 +104,16 @@ int check_sites(const gbr_ctx* c, const gbr_sites& s) {
 }
 
 int check_grid(const gbr_ctx* c, const gbr_grid& g) {
-    if (g.n_inst < 1 || g.nE < 1 || g.npH < 1 || g.nT < 1)
+    if (g.n_inst < 1 || g.nE < 1 || g.npH < 1 || g.nT < 1 || g.nHam < 1)
         return fail(GBR_E_INVAL, "grid sizes must be >= 1");
-    if ((int64_t)g.n_inst * g.nE * g.npH * g.nT != c->n_rep)
-        return fail(GBR_E_INVAL, "grid n_inst*nE*npH*nT (%lld) != n_rep (%d)",
-                    (long long)g.n_inst * g.nE * g.npH * g.nT, c->n_rep);
+    const long long G = (long long)g.n_inst * g.nE * g.npH * g.nT * g.nHam;
+    if (G != c->n_rep)
+        return fail(GBR_E_INVAL, "grid n_inst*nE*npH*nT*nHam (%lld) != n_rep (%d)", G, c->n_rep);
     if (!g.E_vals || !g.pH_vals || !g.T_vals) return fail(GBR_E_INVAL, "grid value table is null");
-    if (g.n_dims < 1 || g.n_dims > 3) return fail(GBR_E_INVAL, "n_dims must be 1..3");
+    if (g.nHam > 1 && !g.H_scale) return fail(GBR_E_INVAL, "nHam > 1 needs H_scale");
+    if (g.n_dims < 1 || g.n_dims > GBR_N_DIMS) return fail(GBR_E_INVAL, "n_dims must be 1..4");
     for (int k = 0; k < g.n_dims; ++k)
-        if (g.dim_order[k] < 0 || g.dim_order[k] > 2) return fail(GBR_E_INVAL, "bad dim_order");
+        if (g.dim_order[k] < 0 || g.dim_order[k] >= GBR_N_DIMS) return fail(GBR_E_INVAL, "bad dim_order");
     return GBR_OK;
 }
 
@@ -184,12 +185,16 @@ int md_one_step(gbr_ctx* c, const MDArgs& a, int kind, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "md last");
     if (kind & STEP_EX) {
         Timed t(c, GBR_K_EXCHANGE, s);
-        e = launch_exchange_inputs(c, a.st, a.pr, c->ex_nH, c->ex_ne, c->ex_eps, s);
+        const bool ham = a.pr.grid.nHam > 1;
+        e = launch_exchange_inputs(c, a.st, a.pr, c->ex_nH, c->ex_ne, c->ex_eps,
+                                   ham ? c->ex_enb : nullptr, s);
         if (e == hipSuccess)
             e = launch_exchange(c, a.pr.grid, 0, c->step, a.pr.ex_every, c->ex_nH, c->ex_ne,
-                                c->ex_eps, a.st.target_idx, a.st.grid_rep, c->ex_vscale,
-                                a.st.ex_stats, a.seed, s);
-        if (e == hipSuccess) e = launch_apply_vscale(c, c->ex_vscale, a.st.v, s);
+                                c->ex_eps, c->ex_enb, a.st.target_idx, a.st.grid_rep,
+                                c->ex_vscale, ham ? c->ex_fscale : nullptr, a.st.ex_stats,
+                                a.seed, s);
+        if (e == hipSuccess)
+            e = launch_apply_swaps(c, a, c->ex_vscale, ham ? c->ex_fscale : nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "exchange");
     }
     return GBR_OK;
@@ -220,9 +225,9 @@ uint64_t hash_args(const MDArgs& a) {
     f.add(t.site_atoms); f.add(t.site_rep); f.add(t.site_type); f.add(t.n_states); f.add(t.state_q);
     f.add(t.state_nH); f.add(t.state_ne); f.add(t.G_ref); f.add(t.ref_value);
     const gbr_grid& g = p.grid;
-    f.add(g.n_inst); f.add(g.nE); f.add(g.npH); f.add(g.nT); f.add(g.E_vals); f.add(g.pH_vals);
-    f.add(g.T_vals); f.add(g.n_dims); f.add(g.dim_order[0]); f.add(g.dim_order[1]);
-    f.add(g.dim_order[2]);
+    f.add(g.n_inst); f.add(g.nE); f.add(g.npH); f.add(g.nT); f.add(g.nHam); f.add(g.E_vals);
+    f.add(g.pH_vals); f.add(g.T_vals); f.add(g.H_scale); f.add(g.n_dims);
+    for (int k = 0; k < GBR_N_DIMS; ++k) f.add(g.dim_order[k]);
     f.add(a.seed);
     return f.h | 1ull;
 }
@@ -332,6 +337,8 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     if ((rc = dev_alloc(&c->ex_ne, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->ex_eps, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->ex_vscale, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->ex_enb, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->ex_fscale, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->step, 2))) return done(rc);
     if ((rc = dev_alloc(&c->err, 1))) return done(rc);
     hipError_t e = hipMemset(c->err, 0, sizeof(uint32_t));
@@ -361,7 +368,8 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     (void)hipFree(c->cull_count);
     (void)hipFree(c->psi_fx); (void)hipFree(c->dEdR_fx); (void)hipFree(c->dEdR); (void)hipFree(c->chain_c);
     (void)hipFree(c->ke_fx); (void)hipFree(c->ex_nH); (void)hipFree(c->ex_ne); (void)hipFree(c->ex_eps);
-    (void)hipFree(c->ex_vscale); (void)hipFree(c->step); (void)hipFree(c->err);
+    (void)hipFree(c->ex_vscale); (void)hipFree(c->ex_enb); (void)hipFree(c->ex_fscale);
+    (void)hipFree(c->step); (void)hipFree(c->err);
     delete c;
     if (have_prev && prev != c_dev) (void)hipSetDevice(prev);
     return GBR_OK;
@@ -524,29 +532,31 @@ int titration_delta_e(gbr_ctx* c, const float* xyz, const float* q, const float*
 }
 
 int remd_exchange(gbr_ctx* c, const gbr_grid* grid, uint64_t attempt, const int32_t* nH,
-                  const int32_t* ne, const double* epsT, int32_t* target_idx, int32_t* grid_rep,
-                  float* vscale, uint32_t* ex_stats, uint64_t seed, hipStream_t s) {
+                  const int32_t* ne, const double* epsT, const double* enb, int32_t* target_idx,
+                  int32_t* grid_rep, float* vscale, uint32_t* ex_stats, uint64_t seed,
+                  hipStream_t s) {
     if (int rc = check_ctx(c)) return rc;
     REQ(grid); REQ(nH); REQ(ne); REQ(epsT); REQ(target_idx); REQ(grid_rep); REQ(vscale);
     if (int rc = check_grid(c, *grid)) return rc;
+    if (grid->nHam > 1) REQ(enb);
     hipError_t e;
     {
         Timed t(c, GBR_K_EXCHANGE, s);
-        e = launch_exchange(c, *grid, attempt, nullptr, 1, nH, ne, epsT, target_idx, grid_rep,
-                            vscale, ex_stats, seed, s);
+        e = launch_exchange(c, *grid, attempt, nullptr, 1, nH, ne, epsT, enb, target_idx, grid_rep,
+                            vscale, nullptr, ex_stats, seed, s);
     }
     if (e != hipSuccess) return hip_fail(e, "exchange");
     return GBR_OK;
 }
 
 int gbr_exchange_inputs(gbr_ctx* c, const gbr_md_state* st, const gbr_md_params* pr, int32_t* nH,
-                        int32_t* ne, double* epsT, hipStream_t s) {
+                        int32_t* ne, double* epsT, double* enb, hipStream_t s) {
     if (int rc = check_ctx(c)) return rc;
     REQ(st); REQ(pr); REQ(nH); REQ(ne); REQ(epsT);
     REQ(st->site_state); REQ(st->target_idx); REQ(st->energy_fx);
     if (int rc = check_sites(c, pr->sites)) return rc;
     if (int rc = check_grid(c, pr->grid)) return rc;
-    hipError_t e = launch_exchange_inputs(c, *st, *pr, nH, ne, epsT, s);
+    hipError_t e = launch_exchange_inputs(c, *st, *pr, nH, ne, epsT, enb, s);
     if (e != hipSuccess) return hip_fail(e, "exchange inputs");
     return GBR_OK;
 }

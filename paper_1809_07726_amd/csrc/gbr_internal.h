@@ -65,7 +65,9 @@ struct gbr_ctx {
     int32_t* ex_nH = nullptr;        // [n_rep]
     int32_t* ex_ne = nullptr;
     double* ex_eps = nullptr;
+    double* ex_enb = nullptr;        // [n_rep] unscaled GB + C + LJ energy
     float* ex_vscale = nullptr;
+    double* ex_fscale = nullptr;     // [n_rep] force factor after Hamiltonian swaps
     uint64_t* step = nullptr;        // [2] current step index (second word unused)
     uint32_t* err = nullptr;         // device error word
     gbr::Timer timer;
@@ -135,12 +137,16 @@ hipError_t launch_titration(const gbr_ctx* c, const float* xyz, const float* q, 
                             double* dE, hipStream_t s);
 hipError_t launch_exchange_inputs(const gbr_ctx* c, const gbr_md_state& st,
                                   const gbr_md_params& pr, int32_t* nH, int32_t* ne,
-                                  double* epsT, hipStream_t s);
+                                  double* epsT, double* enb, hipStream_t s);
 hipError_t launch_exchange(const gbr_ctx* c, const gbr_grid& g, uint64_t attempt,
                            const uint64_t* attempt_from_step, int32_t ex_every,
                            const int32_t* nH, const int32_t* ne, const double* epsT,
-                           int32_t* target_idx, int32_t* grid_rep, float* vscale,
-                           uint32_t* ex_stats, uint64_t seed, hipStream_t s);
-hipError_t launch_apply_vscale(const gbr_ctx* c, const float* vscale, float* v, hipStream_t s);
+                           const double* enb, int32_t* target_idx, int32_t* grid_rep,
+                           float* vscale, double* fscale, uint32_t* ex_stats, uint64_t seed,
+                           hipStream_t s);
+// Velocity scaling after temperature swaps and force rescaling after
+// Hamiltonian swaps (fscale may be NULL).
+hipError_t launch_apply_swaps(const gbr_ctx* c, const MDArgs& a, const float* vscale,
+                              const double* fscale, hipStream_t s);
 
 }  // namespace gbr

@@ -16,13 +16,24 @@ namespace {
 // Langevin half and its Monte Carlo attempts) advances it to n + 1.
 __global__ void k_set_step(uint64_t* step, uint64_t step0) { step[0] = step0; }
 
+// Scale l of replica rep's GB + Coulomb + LJ energy (its Hamiltonian level).
+__device__ __forceinline__ double ham_scale(const double* __restrict__ H_scale,
+                                            const int32_t* __restrict__ target_idx, int rep) {
+    return H_scale ? H_scale[target_idx[GBR_N_DIMS * rep + GBR_DIM_H]] : 1.0;
+}
+
+// A fixed-point force scaled by l (unchanged, bit for bit, at l = 1).
+__device__ __forceinline__ int64_t scale_fx(int64_t f, double l, uint32_t* err) {
+    return l == 1.0 ? f : to_fixed(l * from_fixed(f, INV_FX_FORCE), FX_FORCE, err);
+}
+
 // ------------------------------------------------------ B, A, O, A stages
 // v += dt/2 F/m;  x += dt/2 v;  v = c1 v + c2 sqrt(kT/m) xi;  x += dt/2 v.
 // Also clears the accumulators of the force evaluation that follows, after
 // handing the previous step's kinetic energy to ke (may be NULL).
 // MID: the kernel also closes the previous step (what k_md_last does, with
-// the same roundings): tether forces at the current positions and the final
-// half kick.  Used when nothing reads the previous step's end state (no
+// the same roundings): the pair forces scaled by the replica's Hamiltonian
+// scale, tether forces at the current positions, and the final half kick.  Used when nothing reads the previous step's end state (no
 // exchange attempt after it, not the last step of the call), so that step's
 // kinetic and tether energies are not formed; the kinetic-energy accumulator
 // then stays at zero.
@@ -31,7 +42,8 @@ __global__ __launch_bounds__(256) void k_md_first(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
     const uint64_t* __restrict__ step, uint64_t seed, double hdt, double c1, double c2,
     const float* __restrict__ mass, const double* __restrict__ T_vals,
-    const int32_t* __restrict__ target_idx, float* __restrict__ xyz, float* __restrict__ v,
+    const double* __restrict__ H_scale, const int32_t* __restrict__ target_idx,
+    float* __restrict__ xyz, float* __restrict__ v,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ psi_fx,
     int64_t* __restrict__ dEdR_fx, int64_t* __restrict__ ke_fx, double* __restrict__ ke,
     const float* __restrict__ x0, double k_t, uint32_t* __restrict__ err)
@@ -51,7 +63,8 @@ __global__ __launch_bounds__(256) void k_md_first(
     if (li >= n) return;
     const int a = a0 + li;
     const uint64_t nstep = step[0];
-    const double kT = KB * T_vals[target_idx[3 * rep + 2]];
+    const double kT = KB * T_vals[target_idx[GBR_N_DIMS * rep + GBR_DIM_T]];
+    const double lam = MID ? ham_scale(H_scale, target_idx, rep) : 1.0;
     const double im = ACC_CONV / (double)mass[a];
     const double sd = sqrt(kT * im);
     double xi[4];
@@ -64,7 +77,7 @@ __global__ __launch_bounds__(256) void k_md_first(
         int64_t f = force_fx[idx];
         if (MID) {
             const double dx = xx - (double)x0[idx];
-            f += to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
+            f = scale_fx(f, lam, err) + to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
             vv = (double)(float)(vv + hdt * from_fixed(f, INV_FX_FORCE) * im);
         }
         vv += hdt * from_fixed(f, INV_FX_FORCE) * im;
@@ -79,11 +92,13 @@ __global__ __launch_bounds__(256) void k_md_first(
     dEdR_fx[a] = 0;
 }
 
-// Tether k |x - x0|^2 added to the forces and the replica's energy slot 3;
-// then (kick) v += dt/2 F/m and the kinetic energy.
+// The pair forces scaled by the replica's Hamiltonian scale, plus the tether
+// k |x - x0|^2 (its energy in the replica's slot 3); then (kick) v += dt/2 F/m
+// and the kinetic energy.
 __global__ __launch_bounds__(256) void k_md_last(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
-    int ntot, double hdt, double k_t, const float* __restrict__ mass,
+    int ntot, double hdt, double k_t, const double* __restrict__ H_scale,
+    const int32_t* __restrict__ target_idx, const float* __restrict__ mass,
     const float* __restrict__ x0, const float* __restrict__ xyz, float* __restrict__ v,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx,
     int kick, uint32_t* __restrict__ err)
@@ -99,12 +114,13 @@ __global__ __launch_bounds__(256) void k_md_last(
     if (li < n) {
         const int a = a0 + li;
         const double m = mass[a], im = ACC_CONV / m;
+        const double lam = ham_scale(H_scale, target_idx, rep);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int64_t idx = (int64_t)d * ntot + a;
             const double dx = (double)xyz[idx] - (double)x0[idx];
             et += k_t * dx * dx;
-            const int64_t f = force_fx[idx] + to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
+            const int64_t f = scale_fx(force_fx[idx], lam, err) + to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
             force_fx[idx] = f;
             double vv = v[idx];
             if (kick) {
@@ -257,8 +273,9 @@ __global__ __launch_bounds__(TB) void k_titration(
 }
 
 // One protonation attempt, then one redox attempt, for replica blockIdx.x.
-//   dG = dE - [G_ref(s') - G_ref(s)] + kT ln10 (pH - pKa_ref)(N_H(s') - N_H(s))   (pH)
-//   dG = dE - [G_ref(s') - G_ref(s)] + F (E - E0_ref)(N_e(s') - N_e(s))            (redox)
+//   dG = l dE - [G_ref(s') - G_ref(s)] + kT ln10 (pH - pKa_ref)(N_H(s') - N_H(s))   (pH)
+//   dG = l dE - [G_ref(s') - G_ref(s)] + F (E - E0_ref)(N_e(s') - N_e(s))            (redox)
+// (l: the replica's Hamiltonian scale)
 // accepted iff dG <= 0 or u < exp(-dG/kT); accepted charges are written before
 // the next attempt reads q.
 __global__ __launch_bounds__(TB) void k_mc(
@@ -310,15 +327,17 @@ __global__ __launch_bounds__(TB) void k_mc(
         const double dEel = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau, sc);
         if (threadIdx.x == 0) {
             const int cur = site_state[site];
-            const double T = G.T_vals[target_idx[3 * rep + 2]];
+            const int32_t* tg = target_idx + GBR_N_DIMS * rep;
+            const double T = G.T_vals[tg[GBR_DIM_T]];
             const double kT = KB * T;
-            double dG = dEel - (S.G_ref[site * ms + nw] - S.G_ref[site * ms + cur]);
+            const double lam = ham_scale(G.H_scale, target_idx, rep);
+            double dG = lam * dEel - (S.G_ref[site * ms + nw] - S.G_ref[site * ms + cur]);
             if (type == 0) {
-                const double pH = G.pH_vals[target_idx[3 * rep + 1]];
+                const double pH = G.pH_vals[tg[GBR_DIM_PH]];
                 dG += kT * LN10 * (pH - S.ref_value[site])
                       * (double)(S.state_nH[site * ms + nw] - S.state_nH[site * ms + cur]);
             } else {
-                const double Ev = G.E_vals[target_idx[3 * rep + 0]];
+                const double Ev = G.E_vals[tg[GBR_DIM_E]];
                 dG += FARADAY * (Ev - S.ref_value[site])
                       * (double)(S.state_ne[site * ms + nw] - S.state_ne[site * ms + cur]);
             }
@@ -341,21 +360,23 @@ __global__ __launch_bounds__(TB) void k_mc(
 }
 
 // --------------------------------------------------------- replica exchange
-// Per replica: protons, electrons and the energy entering the temperature
-// exchange: U - sum G_ref(s) + sum_redox F (E - E0_ref) N_e(s)  (mode 0) or U (mode 1).
+// Per replica: protons, electrons, the energy entering the temperature
+// exchange, U_l - sum G_ref(s) + sum_redox F (E - E0_ref) N_e(s)  (mode 0) or U_l
+// (mode 1) with U_l = l (E_GB + E_C + E_LJ) + E_tether, and (enb, may be NULL)
+// the unscaled E_GB + E_C + E_LJ that the Hamiltonian exchange compares.
 __global__ void k_exchange_inputs(int n_rep, gbr_sites S, gbr_grid G,
                                   const int32_t* __restrict__ site_state,
                                   const int32_t* __restrict__ target_idx,
                                   const int64_t* __restrict__ energy_fx, int eps_mode,
                                   int32_t* __restrict__ nH, int32_t* __restrict__ ne,
-                                  double* __restrict__ epsT)
+                                  double* __restrict__ epsT, double* __restrict__ enb)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_rep) return;
     const int ms = S.max_states;
     int h = 0, e = 0;
     double extra = 0.0;
-    const double Ev = G.E_vals[target_idx[3 * r]];
+    const double Ev = G.E_vals[target_idx[GBR_N_DIMS * r + GBR_DIM_E]];
     if (S.rep_site_off) {
         for (int k = S.rep_site_off[r]; k < S.rep_site_off[r + 1]; ++k) {
             const int st = site_state[k];
@@ -366,23 +387,28 @@ __global__ void k_exchange_inputs(int n_rep, gbr_sites S, gbr_grid G,
                 extra += FARADAY * (Ev - S.ref_value[k]) * (double)S.state_ne[k * ms + st];
         }
     }
-    double U = 0.0;
-    for (int c = 0; c < 4; ++c) U += from_fixed(energy_fx[4 * r + c], INV_FX_ENERGY);
+    double W = 0.0;
+    for (int c = 0; c < 3; ++c) W += from_fixed(energy_fx[4 * r + c], INV_FX_ENERGY);
+    const double U = ham_scale(G.H_scale, target_idx, r) * W + from_fixed(energy_fx[4 * r + 3], INV_FX_ENERGY);
     nH[r] = h;
     ne[r] = e;
     epsT[r] = eps_mode == 0 ? U + extra : U;
+    if (enb) enb[r] = W;
 }
 
 // One thread per grid point.  The attempt index is `attempt` or, when
 // step_dev is given, (step + 1) / ex_every - 1 for the step being executed.
+// fscale (may be NULL) receives l_new / l_old for replicas whose Hamiltonian
+// level changed and 1 otherwise.
 __global__ void k_exchange(gbr_grid G, uint64_t attempt, const uint64_t* __restrict__ step_dev,
                            int ex_every, const int32_t* __restrict__ nH,
                            const int32_t* __restrict__ ne, const double* __restrict__ epsT,
-                           int32_t* __restrict__ target_idx, int32_t* __restrict__ grid_rep,
-                           float* __restrict__ vscale, uint32_t* __restrict__ ex_stats,
+                           const double* __restrict__ enb, int32_t* __restrict__ target_idx,
+                           int32_t* __restrict__ grid_rep, float* __restrict__ vscale,
+                           double* __restrict__ fscale, uint32_t* __restrict__ ex_stats,
                            uint64_t seed)
 {
-    const int Gp = G.nE * G.npH * G.nT;
+    const int Gp = G.nE * G.npH * G.nT * G.nHam;
     const int gg = blockIdx.x * blockDim.x + threadIdx.x;
     if (gg >= Gp * G.n_inst) return;
     // step_dev[0] = n + 1 once the step's force evaluation and kick are done
@@ -390,29 +416,36 @@ __global__ void k_exchange(gbr_grid G, uint64_t attempt, const uint64_t* __restr
     const int d = G.dim_order[a % (uint64_t)G.n_dims];
     const int parity = (int)((a / (uint64_t)G.n_dims) & 1);
     const int inst = gg / Gp, g = gg % Gp;
-    const int c[3] = {g / (G.npH * G.nT), (g / G.nT) % G.npH, g % G.nT};
-    const int sz[3] = {G.nE, G.npH, G.nT};
+    const int c[GBR_N_DIMS] = {g / (G.npH * G.nT * G.nHam), (g / (G.nT * G.nHam)) % G.npH,
+                               (g / G.nHam) % G.nT, g % G.nHam};
+    const int sz[GBR_N_DIMS] = {G.nE, G.npH, G.nT, G.nHam};
     const int k = c[d];
     const bool lower = (k & 1) == parity && k + 1 < sz[d];
     const bool upper = k >= 1 && ((k - 1) & 1) == parity;
     const int ri = grid_rep[gg];
     if (!lower) {
-        if (!upper) vscale[ri] = 1.0f;
+        if (!upper) {
+            vscale[ri] = 1.0f;
+            if (fscale) fscale[ri] = 1.0;
+        }
         return;
     }
-    int c2[3] = {c[0], c[1], c[2]};
+    int c2[GBR_N_DIMS] = {c[0], c[1], c[2], c[3]};
     c2[d] = k + 1;
-    const int gu = inst * Gp + (c2[0] * G.npH + c2[1]) * G.nT + c2[2];
+    const int gu = inst * Gp + ((c2[0] * G.npH + c2[1]) * G.nT + c2[2]) * G.nHam + c2[3];
     const int rj = grid_rep[gu];
     double delta;
     if (d == GBR_DIM_PH) {
         delta = LN10 * (G.pH_vals[k] - G.pH_vals[k + 1]) * (double)(nH[ri] - nH[rj]);
     } else if (d == GBR_DIM_E) {
-        const double kT = KB * G.T_vals[c[2]];
+        const double kT = KB * G.T_vals[c[GBR_DIM_T]];
         delta = FARADAY / kT * (G.E_vals[k] - G.E_vals[k + 1]) * (double)(ne[ri] - ne[rj]);
-    } else {
+    } else if (d == GBR_DIM_T) {
         const double bi = 1.0 / (KB * G.T_vals[k]), bj = 1.0 / (KB * G.T_vals[k + 1]);
         delta = (bi - bj) * (epsT[ri] - epsT[rj]);
+    } else {
+        const double kT = KB * G.T_vals[c[GBR_DIM_T]];
+        delta = (G.H_scale[k] - G.H_scale[k + 1]) / kT * (enb[ri] - enb[rj]);
     }
     const U4 w = draw(seed, 0u, (uint32_t)gg, a, STREAM_EX);
     const double u = uniform53(w.x, w.y);
@@ -420,25 +453,40 @@ __global__ void k_exchange(gbr_grid G, uint64_t attempt, const uint64_t* __restr
     const int GT = Gp * G.n_inst;
     if (ex_stats) {
         ex_stats[d * GT + gg] += 1;
-        if (acc) ex_stats[3 * GT + d * GT + gg] += 1;
+        if (acc) ex_stats[GBR_N_DIMS * GT + d * GT + gg] += 1;
     }
     float si = 1.0f, sj = 1.0f;
+    double fi = 1.0, fj = 1.0;
     if (acc) {
-        target_idx[3 * ri + d] = k + 1;
-        target_idx[3 * rj + d] = k;
+        target_idx[GBR_N_DIMS * ri + d] = k + 1;
+        target_idx[GBR_N_DIMS * rj + d] = k;
         grid_rep[gg] = rj;
         grid_rep[gu] = ri;
         if (d == GBR_DIM_T) {
             si = (float)sqrt(G.T_vals[k + 1] / G.T_vals[k]);
             sj = (float)sqrt(G.T_vals[k] / G.T_vals[k + 1]);
+        } else if (d == GBR_DIM_H) {
+            fi = G.H_scale[k + 1] / G.H_scale[k];
+            fj = G.H_scale[k] / G.H_scale[k + 1];
         }
     }
     vscale[ri] = si;
     vscale[rj] = sj;
+    if (fscale) {
+        fscale[ri] = fi;
+        fscale[rj] = fj;
+    }
 }
 
-__global__ void k_apply_vscale(int ntot, int n_rep, const int32_t* __restrict__ atom_off,
-                               const float* __restrict__ vscale, float* __restrict__ v)
+// After an exchange attempt: velocities of replicas whose temperature changed
+// times vscale; with fscale, the forces of replicas whose Hamiltonian level
+// changed made those of the new level: the pair part (the force less the
+// tether term k_md_last added, the same integer) times l_new / l_old.
+__global__ void k_apply_swaps(int ntot, int n_rep, const int32_t* __restrict__ atom_off,
+                              const float* __restrict__ vscale, float* __restrict__ v,
+                              const double* __restrict__ fscale, const float* __restrict__ xyz,
+                              const float* __restrict__ x0, double k_t,
+                              int64_t* __restrict__ force_fx, uint32_t* __restrict__ err)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= ntot) return;
@@ -452,6 +500,16 @@ __global__ void k_apply_vscale(int ntot, int n_rep, const int32_t* __restrict__ 
         v[a] *= s;
         v[ntot + a] *= s;
         v[2 * ntot + a] *= s;
+    }
+    const double fs = fscale ? fscale[lo] : 1.0;
+    if (fs != 1.0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int64_t idx = (int64_t)d * ntot + a;
+            const double dx = (double)xyz[idx] - (double)x0[idx];
+            const int64_t ft = to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
+            force_fx[idx] = scale_fx(force_fx[idx] - ft, fs, err) + ft;
+        }
     }
 }
 
@@ -472,7 +530,7 @@ hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, bool mid, hipStrea
     const double c2 = sqrt(1.0 - c1 * c1);
 #define GBR_MDF(MID) hipLaunchKernelGGL(k_md_first<MID>, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, \
         c->n_tiles, c->atom_off, c->n_atoms, c->step, a.seed, hdt, c1, c2, a.pr.mass, a.pr.grid.T_vals, \
-        a.st.target_idx, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->psi_fx, c->dEdR_fx, \
+        a.pr.grid.H_scale, a.st.target_idx, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->psi_fx, c->dEdR_fx, \
         c->ke_fx, a.st.ke, a.pr.x0, a.pr.k_tether, c->err)
     if (mid) GBR_MDF(true); else GBR_MDF(false);
 #undef GBR_MDF
@@ -481,8 +539,8 @@ hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, bool mid, hipStrea
 
 hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s) {
     hipLaunchKernelGGL(k_md_last, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
-                       c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.mass,
-                       a.pr.x0, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx,
+                       c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.grid.H_scale,
+                       a.st.target_idx, a.pr.mass, a.pr.x0, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx,
                        kick, c->err);
     return hipGetLastError();
 }
@@ -524,29 +582,32 @@ hipError_t launch_titration(const gbr_ctx* c, const float* xyz, const float* q, 
 
 hipError_t launch_exchange_inputs(const gbr_ctx* c, const gbr_md_state& st,
                                   const gbr_md_params& pr, int32_t* nH, int32_t* ne,
-                                  double* epsT, hipStream_t s) {
+                                  double* epsT, double* enb, hipStream_t s) {
     hipLaunchKernelGGL(k_exchange_inputs, dim3((c->n_rep + 127) / 128), dim3(128), 0, s, c->n_rep,
                        pr.sites, pr.grid, st.site_state, st.target_idx, st.energy_fx, pr.eps_mode,
-                       nH, ne, epsT);
+                       nH, ne, epsT, enb);
     return hipGetLastError();
 }
 
 hipError_t launch_exchange(const gbr_ctx* c, const gbr_grid& g, uint64_t attempt,
                            const uint64_t* attempt_from_step, int32_t ex_every,
                            const int32_t* nH, const int32_t* ne, const double* epsT,
-                           int32_t* target_idx, int32_t* grid_rep, float* vscale,
-                           uint32_t* ex_stats, uint64_t seed, hipStream_t s) {
+                           const double* enb, int32_t* target_idx, int32_t* grid_rep,
+                           float* vscale, double* fscale, uint32_t* ex_stats, uint64_t seed,
+                           hipStream_t s) {
     (void)c;
-    const int total = g.n_inst * g.nE * g.npH * g.nT;
+    const int total = g.n_inst * g.nE * g.npH * g.nT * g.nHam;
     hipLaunchKernelGGL(k_exchange, dim3((total + 127) / 128), dim3(128), 0, s, g, attempt,
-                       attempt_from_step, ex_every, nH, ne, epsT, target_idx, grid_rep, vscale,
-                       ex_stats, seed);
+                       attempt_from_step, ex_every, nH, ne, epsT, enb, target_idx, grid_rep, vscale,
+                       fscale, ex_stats, seed);
     return hipGetLastError();
 }
 
-hipError_t launch_apply_vscale(const gbr_ctx* c, const float* vscale, float* v, hipStream_t s) {
-    hipLaunchKernelGGL(k_apply_vscale, dim3((c->n_atoms + 255) / 256), dim3(256), 0, s,
-                       c->n_atoms, c->n_rep, c->atom_off, vscale, v);
+hipError_t launch_apply_swaps(const gbr_ctx* c, const MDArgs& a, const float* vscale,
+                              const double* fscale, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply_swaps, dim3((c->n_atoms + 255) / 256), dim3(256), 0, s,
+                       c->n_atoms, c->n_rep, c->atom_off, vscale, a.st.v, fscale, a.st.xyz,
+                       a.pr.x0, a.pr.k_tether, a.st.force_fx, c->err);
     return hipGetLastError();
 }
 

@@ -132,10 +132,10 @@ class Context:
         return dE
 
     def remd_exchange(self, grid: A.Grid, attempt, nH, ne, epsT, target_idx, grid_rep, seed,
-                      ex_stats=None, stream=None):
+                      ex_stats=None, enb=None, stream=None):
         vscale = self._new(self.n_rep, F32)
         check(A.lib.remd_exchange(self.h, C.byref(grid), int(attempt), ptr(nH, I32), ptr(ne, I32),
-                                  ptr(epsT, F64), ptr(target_idx, I32), ptr(grid_rep, I32),
+                                  ptr(epsT, F64), ptr(enb, F64), ptr(target_idx, I32), ptr(grid_rep, I32),
                                   ptr(vscale), ptr(ex_stats, torch.int32), int(seed),
                                   stream_handle(stream)))
         return vscale
@@ -177,8 +177,8 @@ class DeviceBatch:
             put("state_q", b["state_q"], F32)
             put("G_ref", b["G_ref"], F64)
             put("ref_value", b["ref_value"], F64)
-        for k in ("E_vals", "pH_vals", "T_vals"):
-            put(k, b[k], F64)
+        for k in ("E_vals", "pH_vals", "T_vals", "H_scale"):
+            put(k, b.get(k, [1.0]) if k == "H_scale" else b[k], F64)
         put("target_idx", np.asarray(b["target_idx"]).reshape(-1), I32)
         put("grid_rep", b["grid_rep"], I32)
         sites = A.Sites()
@@ -191,11 +191,13 @@ class DeviceBatch:
         grid = A.Grid()
         grid.n_inst = int(b["n_inst"])
         grid.nE, grid.npH, grid.nT = len(b["E_vals"]), len(b["pH_vals"]), len(b["T_vals"])
+        grid.nHam = t["H_scale"].numel()
         grid.E_vals, grid.pH_vals, grid.T_vals = (t["E_vals"].data_ptr(), t["pH_vals"].data_ptr(),
                                                   t["T_vals"].data_ptr())
+        grid.H_scale = t["H_scale"].data_ptr()
         order = list(b["dim_order"])
         grid.n_dims = len(order)
-        for k in range(3):
+        for k in range(A.N_DIMS):
             grid.dim_order[k] = order[k] if k < len(order) else 0
         return DeviceBatch(t, sites, grid, int(b["n_rep"]), int(b["atom_off"][-1]))
 
@@ -218,9 +220,9 @@ class MD:
         self.dRdpsi = torch.zeros(N, dtype=F32, device=dev)
         self.ke = torch.zeros(R, dtype=F64, device=dev)
         ns = batch.sites.n_sites
-        G = int(b["n_inst"]) * len(b["E_vals"]) * len(b["pH_vals"]) * len(b["T_vals"])
+        G = R                   # one grid point per replica
         self.mc_stats = torch.zeros(2 * max(ns, 1), dtype=torch.int32, device=dev) if stats else None
-        self.ex_stats = torch.zeros(6 * G, dtype=torch.int32, device=dev) if stats else None
+        self.ex_stats = torch.zeros(2 * A.N_DIMS * G, dtype=torch.int32, device=dev) if stats else None
         st = A.MDState()
         st.xyz, st.v, st.q = t["xyz"].data_ptr(), t["v"].data_ptr(), t["q"].data_ptr()
         st.force_fx, st.energy_fx = self.force_fx.data_ptr(), self.energy_fx.data_ptr()
@@ -247,13 +249,15 @@ class MD:
         self.step += int(n_steps)
 
     def exchange_inputs(self, stream=None):
+        """(N_H, N_e, epsT, enb) per replica, as md_step's exchange reads them."""
         R = self.ctx.n_rep
         nH = torch.empty(R, dtype=I32, device=self.ctx.device)
         ne = torch.empty(R, dtype=I32, device=self.ctx.device)
         ep = torch.empty(R, dtype=F64, device=self.ctx.device)
+        enb = torch.empty(R, dtype=F64, device=self.ctx.device)
         check(A.lib.gbr_exchange_inputs(self.ctx.h, C.byref(self.st), C.byref(self.pr), ptr(nH),
-                                        ptr(ne), ptr(ep), stream_handle(stream)))
-        return nH, ne, ep
+                                        ptr(ne), ptr(ep), ptr(enb), stream_handle(stream)))
+        return nH, ne, ep, enb
 
 
 # ------------------------------------------------------------- autograd

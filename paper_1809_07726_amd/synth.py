@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 PH_SITE, REDOX_SITE = 0, 1
-DIM_E, DIM_PH, DIM_T = 0, 1, 2
+DIM_E, DIM_PH, DIM_T, DIM_H = 0, 1, 2, 3
 
 
 @dataclass(frozen=True)
@@ -164,15 +164,17 @@ def jitter_copy(sysd: dict, seed: int):
 
 
 def assemble(systems: list, reps_per_system: int, E_vals, pH_vals, T_vals, dim_order,
-             per_replica: list | None = None, **md):
+             per_replica: list | None = None, H_scale=(1.0,), **md):
     """Flatten replicas of each system back to back and build the site tables
     and the replica grid (one grid instance per system; replica k of a system
-    starts at grid point k, g = (iE * npH + ipH) * nT + iT).
+    starts at grid point k, g = ((iE * npH + ipH) * nT + iT) * nHam + iH, with
+    H_scale the scales of the GB + Coulomb + LJ energy at the Hamiltonian
+    levels).
 
     ``per_replica`` optionally gives a distinct system dict (same topology) for
     every replica."""
-    nE, npH, nT = len(E_vals), len(pH_vals), len(T_vals)
-    G = nE * npH * nT
+    nE, npH, nT, nHam = len(E_vals), len(pH_vals), len(T_vals), len(H_scale)
+    G = nE * npH * nT * nHam
     if reps_per_system != G:
         raise ValueError("replicas per system must equal the grid size")
     reps = per_replica or [s for s in systems for _ in range(reps_per_system)]
@@ -215,11 +217,12 @@ def assemble(systems: list, reps_per_system: int, E_vals, pH_vals, T_vals, dim_o
     # grid
     n_inst = len(systems) if per_replica is None else len(reps) // reps_per_system
     g = np.arange(out["n_rep"]) % G
-    out["target_idx"] = np.stack([g // (npH * nT), (g // nT) % npH, g % nT], axis=1).astype(np.int32)
+    out["target_idx"] = np.stack([g // (npH * nT * nHam), (g // (nT * nHam)) % npH,
+                                  (g // nHam) % nT, g % nHam], axis=1).astype(np.int32)
     out["grid_rep"] = np.arange(out["n_rep"], dtype=np.int32)
     out.update({"n_inst": n_inst, "E_vals": np.asarray(E_vals, np.float64),
                 "pH_vals": np.asarray(pH_vals, np.float64), "T_vals": np.asarray(T_vals, np.float64),
-                "dim_order": list(dim_order)})
+                "H_scale": np.asarray(H_scale, np.float64), "dim_order": list(dim_order)})
     out["v"] = np.zeros_like(out["xyz"])
     out.update({"k_tether": K_TETHER, "dt": DT, "gamma_ps": GAMMA, "mc_every": 10, "ex_every": 0})
     out.update(md)

@@ -126,26 +126,34 @@ def four_state_constants(eps, T, pKa, E0):
             "E0_prot": E0 - (eps[1, 1] - eps[1, 0]) / c["F"]}
 
 
-def diprotic_site_batch(pH, seed=31, reps=1):
+def diprotic_site_batch(pH, seed=31, reps=1, tautomer=False):
     """One isolated pH site (its atoms only, from a 64-atom lattice system),
-    frozen (dt = 0), attempts every step, with a third state holding a second
-    proton (N_H = 0, 1, 2); reps independent copies, one replica each.  G_ref
-    is left for the caller."""
+    frozen (dt = 0), attempts every step, with a third state: a second proton
+    (N_H = 0, 1, 2), or with tautomer=True a second protonated tautomer (N_H =
+    0, 1, 1: the proton's charge increments of state 1 laid on the site's atoms
+    in reverse order, the same net charge distributed differently); reps
+    independent copies, one replica each.  G_ref is left for the caller."""
     b = synth.make_config(0, n_atoms=64, seed=seed)
     a, c = b["site_off"][0], b["site_off"][1]
     idx = b["site_atoms"][a:c]
     q2 = b["state_q"].reshape(-1, 2)[a:c]
     sysd = {k: b[k][idx] for k in ("xyz", "x0", "q", "rho", "screen", "sigma", "eps", "mass")}
+    if tautomer:
+        third, nH = q2[:, 0] + (q2[:, 1] - q2[:, 0])[::-1], [0, 1, 1]
+    else:
+        third, nH = 2 * q2[:, 1] - q2[:, 0], [0, 1, 2]
     sysd["sites"] = [{"type": synth.PH_SITE, "atoms": np.arange(c - a),
-                      "q_states": np.stack([q2[:, 0], q2[:, 1], 2 * q2[:, 1] - q2[:, 0]], axis=1),
-                      "nH": [0, 1, 2], "ne": [0, 0, 0], "ref": b["ref_value"][0]}]
+                      "q_states": np.stack([q2[:, 0], q2[:, 1], third], axis=1),
+                      "nH": nH, "ne": [0, 0, 0], "ref": b["ref_value"][0]}]
     return synth.assemble([sysd] * reps, 1, (-0.2,), (pH,), (300.0,), (0,), dt=0.0, mc_every=1)
 
 
-def three_state_expected(d):
-    """Occupancies of N_H = 0, 1, 2 for an isolated site at pH - pKa_ref = d:
-    the attempts sample exp(-G/kT) with G(s) = kT ln10 (pH - pKa) N_H(s)."""
-    w = np.array([1.0, 10.0 ** -d, 10.0 ** (-2 * d)])
+def three_state_expected(d, tautomer=False):
+    """Occupancies of the three states of diprotic_site_batch at pH - pKa_ref =
+    d with G_ref from the site alone (so that dE_elec - dG_ref = 0): the
+    attempts sample exp(-G/kT) with G(s) = kT ln10 (pH - pKa) N_H(s), N_H =
+    (0, 1, 2), or (0, 1, 1) for two tautomers."""
+    w = np.array([1.0, 10.0 ** -d, 10.0 ** (-d if tautomer else -2 * d)])
     return w / w.sum()
 
 

@@ -57,24 +57,28 @@ def test_eqs_6_7_8_against_enumeration_of_the_coupled_model():
 
 
 def test_residence_histogram_and_acceptance_bookkeeping():
-    # 2 x 1 x 2 grid (E, pH, T), 4 replicas; replica 0 walks 0 -> 1 -> 3 -> 3
+    # 2 x 1 x 2 x 1 grid (E, pH, T, H), 4 replicas; replica 0 walks 0 -> 1 -> 3 -> 3
     nE, npH, nT = 2, 1, 2
     snaps = np.array([
-        [[0, 0, 0], [0, 0, 1], [1, 0, 0], [1, 0, 1]],
-        [[0, 0, 1], [0, 0, 0], [1, 0, 0], [1, 0, 1]],
-        [[1, 0, 1], [0, 0, 0], [1, 0, 0], [0, 0, 1]],
-        [[1, 0, 1], [0, 0, 0], [1, 0, 0], [0, 0, 1]],
+        [[0, 0, 0, 0], [0, 0, 1, 0], [1, 0, 0, 0], [1, 0, 1, 0]],
+        [[0, 0, 1, 0], [0, 0, 0, 0], [1, 0, 0, 0], [1, 0, 1, 0]],
+        [[1, 0, 1, 0], [0, 0, 0, 0], [1, 0, 0, 0], [0, 0, 1, 0]],
+        [[1, 0, 1, 0], [0, 0, 0, 0], [1, 0, 0, 0], [0, 0, 1, 0]],
     ])
     h = A.residence_histogram(snaps, nE, npH, nT)
     assert h[0].tolist() == [1, 1, 0, 2]
     assert h.sum() == 16
     s = A.walk_summary(h)
     assert not s["visited_all"][0] and s["worst_ratio"] == math.inf
-    ex = np.zeros(2 * 3 * 4, np.int64)
-    ex[0 * 4 + 0] = 10; ex[12 + 0 * 4 + 0] = 4          # E attempts / accepts at point 0
-    ex[2 * 4 + 1] = 5; ex[12 + 2 * 4 + 1] = 5           # T at point 1
+    ex = np.zeros(2 * 4 * 4, np.int64)
+    ex[0 * 4 + 0] = 10; ex[16 + 0 * 4 + 0] = 4          # E attempts / accepts at point 0
+    ex[2 * 4 + 1] = 5; ex[16 + 2 * 4 + 1] = 5           # T at point 1
     r = A.exchange_acceptance(ex, 1, nE, npH, nT)
     assert r["E"]["rate"] == 0.4 and r["T"]["rate"] == 1.0 and math.isnan(r["pH"]["rate"])
+    assert math.isnan(r["H"]["rate"])
+    # the same walk on a 1 x 1 x 2 x 2 grid (T, H): g = iT * nHam + iH
+    snaps_h = snaps[..., [3, 1, 0, 2]]
+    assert np.array_equal(A.residence_histogram(snaps_h, 1, 1, 2, 2), h)
 
 
 def test_oracle_remd_walk_and_e0_fits_follow_eq7():
@@ -99,7 +103,7 @@ def test_oracle_remd_walk_and_e0_fits_follow_eq7():
         oracle.md_run(cfg, st, step, 4, False)
         step += 4
         states.append(arr["site_state"].copy())
-        targets.append(arr["target_idx"].reshape(-1, 3).copy())
+        targets.append(arr["target_idx"].reshape(-1, 4).copy())
     h = A.residence_histogram(targets, len(Es), len(pHs), 1)
     assert A.walk_summary(h)["fraction_visited_all"] == 1.0
     occ, n = A.fractions_per_point(states, targets, b["rep_site_off"], len(Es), len(pHs), 1)

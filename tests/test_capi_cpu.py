@@ -52,7 +52,7 @@ def test_host_side_argument_checks():
     assert L.gbr_set_launch(None, 4, 8) == A.GBR_E_INVAL
     assert L.gbr_set_timing(None, 1) == A.GBR_E_INVAL
     assert L.md_step(None, None, None, 0, 0, 1, 0, None) == A.GBR_E_INVAL
-    assert L.remd_exchange(None, None, 0, None, None, None, None, None, None, None, 0, None) == A.GBR_E_INVAL
+    assert L.remd_exchange(None, None, 0, None, None, None, None, None, None, None, None, 0, None) == A.GBR_E_INVAL
     assert L.titration_delta_e(None, None, None, None, None, None, 0, None, None) == A.GBR_E_INVAL
     assert L.gb_energy_forces(None, *([None] * 11), 0, None, None, None) == A.GBR_E_INVAL
 

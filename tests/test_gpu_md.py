@@ -11,7 +11,7 @@ import torch
 import oracle
 from common import (batch_mean_bound, diprotic_site_batch, three_state_expected, with_diprotic_ph_sites,
                     with_oracle_gref)
-from gpu_common import FX_E, soa_to_aos
+from gpu_common import FX_E, FX_F, soa_to_aos
 from paper_1809_07726_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -33,7 +33,7 @@ def _gpu_md(b, seed, steps_chunks, graph=False, init=True, params=None):
             "xyz": soa_to_aos(d.t["xyz"].cpu().numpy(), N), "v": soa_to_aos(d.t["v"].cpu().numpy(), N),
             "q": d.t["q"].cpu().numpy().astype(np.float64),
             "site_state": d.t["site_state"].cpu().numpy().copy() if b["n_sites"] else None,
-            "target_idx": d.t["target_idx"].cpu().numpy().reshape(-1, 3).copy(),
+            "target_idx": d.t["target_idx"].cpu().numpy().reshape(-1, 4).copy(),
             "grid_rep": d.t["grid_rep"].cpu().numpy().copy(),
             "E": md.energy_fx.cpu().numpy().reshape(-1, 4) * FX_E,
             "F_fx": md.force_fx.cpu().numpy().copy(),
@@ -53,7 +53,8 @@ def _oracle_md(b, seed, steps_chunks, gb=None):
         oracle.md_run(cfg, st, step, n, False)
         step += n
         snaps.append({k: arr[k].copy() for k in ("xyz", "v", "q", "site_state", "target_idx",
-                                                 "grid_rep", "E", "mc_att", "mc_acc")})
+                                                 "grid_rep", "E", "F", "mc_att", "mc_acc",
+                                                 "ex_att", "ex_acc")})
     return snaps
 
 
@@ -108,10 +109,39 @@ def test_replica_grid_md_with_exchanges_matches_oracle():
     g = _gpu_md(b, 31, chunks)
     o = _oracle_md(b, 31, chunks)
     for gs, os_ in zip(g, o):
-        assert np.array_equal(gs["target_idx"], os_["target_idx"].reshape(-1, 3))
+        assert np.array_equal(gs["target_idx"], os_["target_idx"].reshape(-1, 4))
         assert np.array_equal(gs["grid_rep"], os_["grid_rep"])
         assert np.array_equal(gs["site_state"], os_["site_state"])
         assert np.abs(gs["xyz"] - os_["xyz"].reshape(-1, 3)).max() < 1e-3
+
+
+def test_hamiltonian_grid_md_matches_oracle():
+    """A 2 T x 3 H grid (Hamiltonian scales 1.0, 0.9, 0.8 of the GB + Coulomb
+    + LJ energy), 2 instances, MC and exchanges every 5 steps, T and H
+    attempts alternating: targets, states and positions follow the oracle,
+    and the forces at the end of each call (an exchange step, so the replicas
+    that changed level hold forces rescaled to the new level) match its fresh
+    evaluation."""
+    base = synth.draw_system(160, 4343, 2, 1)
+    reps = [synth.jitter_copy(base, 500 + r) for r in range(12)]
+    b = synth.assemble([base, base], 6, (-0.2,), (7.0,), (300.0, 330.0), (synth.DIM_T, synth.DIM_H),
+                       per_replica=reps, H_scale=(1.0, 0.9, 0.8), mc_every=5, ex_every=5)
+    b = with_oracle_gref(b)
+    chunks = [10, 10, 10, 10]
+    g = _gpu_md(b, 41, chunks)
+    o = _oracle_md(b, 41, chunks)
+    N = b["atom_off"][-1]
+    for gs, os_ in zip(g, o):
+        assert np.array_equal(gs["target_idx"], os_["target_idx"].reshape(-1, 4))
+        assert np.array_equal(gs["grid_rep"], os_["grid_rep"])
+        assert np.array_equal(gs["site_state"], os_["site_state"])
+        assert np.abs(gs["xyz"] - os_["xyz"].reshape(-1, 3)).max() < 1e-3
+        F_g = soa_to_aos(gs["F_fx"] * FX_F, N)
+        F_o = os_["F"].reshape(-1, 3)
+        assert np.sqrt(((F_g - F_o) ** 2).sum() / (F_o ** 2).sum()) < 1e-4
+    G = 12
+    acc_H = o[-1]["ex_acc"][synth.DIM_H * G:(synth.DIM_H + 1) * G].sum()
+    assert acc_H > 0 and o[-1]["ex_att"][synth.DIM_H * G:(synth.DIM_H + 1) * G].sum() > acc_H
 
 
 def test_exchange_decisions_match_oracle_on_identical_inputs():
@@ -138,10 +168,48 @@ def test_exchange_decisions_match_oracle_on_identical_inputs():
                                  torch.as_tensor(ne, device="cuda"),
                                  torch.as_tensor(ep, device="cuda"), ti_g, gr_g, seed=123)
         torch.cuda.synchronize()
-        assert np.array_equal(ti_g.cpu().numpy().reshape(-1, 3), ti_o), a
+        assert np.array_equal(ti_g.cpu().numpy().reshape(-1, 4), ti_o), a
         assert np.array_equal(gr_g.cpu().numpy(), gr_o), a
         assert np.allclose(vs_g.cpu().numpy(), vs_o, rtol=1e-6)
         assert acc.sum() > 0
+    ctx.check()
+    ctx.close()
+
+
+def test_exchange_decisions_with_a_hamiltonian_dimension_match_oracle():
+    """2 instances of a 2 E x 2 pH x 2 T x 3 H grid; random counts and energy
+    components (the GPU reads the unscaled E_GB + E_C + E_LJ, the oracle the
+    four components); 16 attempts cycle E, H, T, pH."""
+    from paper_1809_07726_amd.gb import Context, DeviceBatch
+    base = synth.draw_system(16, 78, 0, 0)
+    b = synth.assemble([base, base], 24, (-0.25, -0.2), (6.0, 7.0), (300.0, 320.0),
+                       (synth.DIM_E, synth.DIM_H, synth.DIM_T, synth.DIM_PH), H_scale=(1.0, 0.95, 0.9))
+    cfg, st, arr, keep = oracle.make_md(b, seed=321)
+    d = DeviceBatch.from_numpy(b)
+    ctx = Context(b["atom_off"])
+    rng = np.random.default_rng(9)
+    R = b["n_rep"]
+    ti_o, gr_o = b["target_idx"].copy(), b["grid_rep"].copy()
+    ti_g = torch.as_tensor(ti_o.reshape(-1).copy(), device="cuda")
+    gr_g = torch.as_tensor(gr_o.copy(), device="cuda")
+    n_acc_h = 0
+    for a in range(16):
+        nH = rng.integers(0, 6, R).astype(np.int32)
+        ne = rng.integers(0, 2, R).astype(np.int32)
+        ep = rng.normal(-5000.0, 3.0, R)
+        E4 = np.stack([rng.normal(-300.0, 10.0, R), rng.normal(-50.0, 10.0, R),
+                       rng.normal(-20.0, 5.0, R), rng.uniform(0.0, 5.0, R)], axis=1)
+        ti_o, gr_o, vs_o, att, acc = oracle.exchange(cfg, a, nH, ne, ep, ti_o, gr_o, E4)
+        vs_g = ctx.remd_exchange(d.grid, a, torch.as_tensor(nH, device="cuda"),
+                                 torch.as_tensor(ne, device="cuda"),
+                                 torch.as_tensor(ep, device="cuda"), ti_g, gr_g, seed=321,
+                                 enb=torch.as_tensor(E4[:, :3].sum(1), device="cuda"))
+        torch.cuda.synchronize()
+        assert np.array_equal(ti_g.cpu().numpy().reshape(-1, 4), ti_o), a
+        assert np.array_equal(gr_g.cpu().numpy(), gr_o), a
+        assert np.allclose(vs_g.cpu().numpy(), vs_o, rtol=1e-6)
+        n_acc_h += acc[synth.DIM_H * R:(synth.DIM_H + 1) * R].sum()
+    assert n_acc_h > 0
     ctx.check()
     ctx.close()
 
@@ -206,17 +274,18 @@ def test_md_step_with_three_state_sites_matches_oracle():
     assert g[-1]["mc_stats"][0::2].sum() == o[-1]["mc_att"].sum() == 2 * 25
 
 
-@pytest.mark.parametrize("d", [-0.5, 0.0, 0.5])
-def test_gpu_three_state_site_statistics(d):
-    """64 frozen copies of an isolated three-state pH site (N_H = 0, 1, 2),
+@pytest.mark.parametrize("d,tautomer", [(-0.5, False), (0.0, False), (0.5, False), (-0.5, True), (0.5, True)])
+def test_gpu_three_state_site_statistics(d, tautomer):
+    """64 frozen copies of an isolated three-state pH site (N_H = 0, 1, 2, or
+    a deprotonated state and two protonated tautomers, N_H = 0, 1, 1),
     attempts every step on the GPU: the occupancies follow
     p(s) proportional to 10^(-(pH - pKa) N_H(s))."""
     from paper_1809_07726_amd.gb import MD, Context, DeviceBatch, reference_energies
-    b = diprotic_site_batch(synth.PKA_REF + d, reps=64)
+    b = diprotic_site_batch(synth.PKA_REF + d, reps=64, tautomer=tautomer)
     b["G_ref"] = reference_energies(b)          # the HIP path's own reference compound
     ctx = Context(b["atom_off"])
     dv = DeviceBatch.from_numpy(b)
-    md = MD(ctx, dv, b, seed=950 + int(100 * d))
+    md = MD(ctx, dv, b, seed=950 + int(100 * d) + 7 * tautomer)
     md.run(1, init_forces=True)
     n = 300
     occ = np.zeros((n, 64), np.int64)
@@ -225,7 +294,7 @@ def test_gpu_three_state_site_statistics(d):
         occ[k] = dv.t["site_state"].cpu().numpy()
     ctx.check()
     ctx.close()
-    p = three_state_expected(d)
+    p = three_state_expected(d, tautomer)
     for s in range(3):
         per_rep = (occ == s).mean(0)            # 64 independent chains
         assert abs(per_rep.mean() - p[s]) <= batch_mean_bound(per_rep, 16), (s, per_rep.mean(), p[s])

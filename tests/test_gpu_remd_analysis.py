@@ -29,7 +29,7 @@ def _grid():
 
 def _rates(ex, mc_att, mc_acc, site_type, n_inst):
     r = A.exchange_acceptance(ex, n_inst, 5, 5, len(TS))
-    out = {d: r[d]["rate"] for d in A.DIMS}
+    out = {d: r[d]["rate"] for d in A.DIMS if r[d]["attempts"]}     # dimensions attempted
     for t, name in ((0, "mc_pH"), (1, "mc_redox")):
         m = site_type == t
         out[name] = mc_acc[m].sum() / mc_att[m].sum()
@@ -53,7 +53,7 @@ def test_e_ph_t_remd_walks_acceptance_and_titration_fits():
         ss[i].copy_(d.t["site_state"])
     torch.cuda.synchronize()
     ctx.check()
-    tg = tg.cpu().numpy().reshape(n_snap, -1, 3)
+    tg = tg.cpu().numpy().reshape(n_snap, -1, 4)
     ss = ss.cpu().numpy()
     mc = md.mc_stats.cpu().numpy().astype(np.int64).reshape(-1, 2)
     g_rates = _rates(md.ex_stats.cpu().numpy(), mc[:, 0], mc[:, 1], b["site_type"], n_inst)
@@ -74,6 +74,7 @@ def test_e_ph_t_remd_walks_acceptance_and_titration_fits():
     oracle.md_run(cfg, st, 0, 2000, False)
     o_rates = _rates(np.concatenate([arr["ex_att"], arr["ex_acc"]]), arr["mc_att"], arr["mc_acc"],
                      bo["site_type"], 2)
+    assert set(g_rates) == set(o_rates) == {"E", "pH", "T", "mc_pH", "mc_redox"}
     for key in o_rates:
         assert abs(g_rates[key] - o_rates[key]) < 0.02, (key, g_rates[key], o_rates[key])
 

@@ -476,6 +476,31 @@ def test_mc_three_state_site_samples_boltzmann(d):
         assert abs(hit.mean() - p[s]) <= batch_mean_bound(hit), (s, hit.mean(), p[s])
 
 
+@pytest.mark.parametrize("d", [-0.5, 0.0, 0.5])
+def test_mc_two_tautomers_shift_the_titration_by_log10_2(d):
+    """A site with one deprotonated state and two protonated tautomers of
+    equal reference energy: each tautomer is occupied with weight 10^-(pH -
+    pKa), so the two are equally likely and the protonated fraction
+    2x / (1 + 2x), x = 10^-(pH - pKa), is the single-tautomer curve moved up
+    by log10(2) in pH (the statistical factor of two equivalent microstates)."""
+    b = with_oracle_gref(diprotic_site_batch(synth.PKA_REF + d, tautomer=True))
+    cfg, st, arr, keep = oracle.make_md(b, seed=320 + int(10 * d))
+    oracle.md_run(cfg, st, 0, 1, True)
+    n = 20000
+    states = np.empty(n, np.int64)
+    for k in range(n):
+        oracle.md_run(cfg, st, k + 1, 1, False)
+        states[k] = arr["site_state"][0]
+    x = 10.0 ** -d
+    prot = (states > 0).astype(np.float64)
+    assert abs(prot.mean() - 2 * x / (1 + 2 * x)) <= batch_mean_bound(prot)
+    assert abs(prot.mean() - 1.0 / (1.0 + 10.0 ** (d - math.log10(2.0)))) <= batch_mean_bound(prot)
+    p = three_state_expected(d, tautomer=True)
+    for s in range(3):
+        hit = (states == s).astype(np.float64)
+        assert abs(hit.mean() - p[s]) <= batch_mean_bound(hit), (s, hit.mean(), p[s])
+
+
 # --------------------------- P11: coupled sites reproduce eqs. 6, 7 and 8
 def _coupled_pair(seed=41):
     """A frozen system holding one pH site and one redox site close together."""
@@ -630,6 +655,120 @@ def test_exchange_pairs_only_nearest_neighbours_sharing_other_targets():
             c2 = list(c); c2[dim] += 1
             g2 = (c2[0] * 2 + c2[1]) * 2 + c2[2]
             assert gr[g] == bb["grid_rep"][g2] and gr[g2] == bb["grid_rep"][g]
+
+
+# ------------------------- P12b: the Hamiltonian dimension (H-REMD)
+def _ham_pair(seeds, H_scale, n_atoms=16, **md):
+    """Two replicas of a 16-atom system in independently jittered geometries
+    (seeds), on a one-dimensional Hamiltonian grid with levels H_scale."""
+    base = synth.draw_system(n_atoms, 51, 0, 0)
+    base["sites"] = []
+    reps = [synth.jitter_copy(base, s) for s in seeds]
+    return synth.assemble([base], len(H_scale), (-0.2,), (7.0,), (300.0,), (synth.DIM_H,),
+                          per_replica=reps, H_scale=H_scale, **md)
+
+
+def _U_scaled(xyz, b, lam, r=None):
+    """Potential of the Hamiltonian of scale lam evaluated the long way: the
+    GB, Coulomb and LJ sums with k_e and every epsilon_i multiplied by lam
+    (epsilon_ij = sqrt(epsilon_i epsilon_j) then scales by lam), plus the
+    unscaled tether.  Also returns dU/dx."""
+    sl = slice(None) if r is None else slice(b["atom_off"][r], b["atom_off"][r + 1])
+    gb = oracle.obc2(k_e=332.0522173 * lam)
+    E, gx, _, _ = oracle.gradient(xyz, b["q"][sl], b["rho"][sl], b["screen"][sl], b["sigma"][sl],
+                                  lam * b["eps"][sl].astype(np.float64), gb)
+    et, gt = oracle.tether(xyz, b["x0"][sl], b["k_tether"])
+    return E.sum() + et, gx + gt
+
+
+@pytest.mark.parametrize("seeds,lams", [((3, 4), (1.0, 0.8)), ((4, 3), (1.0, 0.8)),
+                                        ((5, 6), (1.0, 0.9)), ((5, 6), (0.6, 1.3))])
+def test_hamiltonian_exchange_rate_from_scaled_potentials(seeds, lams):
+    """Replica i at level 0, j at level 1 trade Hamiltonians with probability
+    min(1, exp(-[U_0(x_j) + U_1(x_i) - U_0(x_i) - U_1(x_j)] / kT)), the four
+    potentials evaluated with scaled k_e and epsilon rather than from the
+    unscaled energy components the exchange reads."""
+    b = _ham_pair(seeds, lams)
+    cfg, st, arr, keep = oracle.make_md(b, seed=17)
+    oracle.md_run(cfg, st, 0, 0, True)
+    E4 = arr["E"].reshape(2, 4).copy()
+    x = [b["xyz"][b["atom_off"][r]:b["atom_off"][r + 1]] for r in (0, 1)]
+    U = lambda r, lam: _U_scaled(x[r], b, lam, r)[0]
+    delta = -(U(1, lams[0]) + U(0, lams[1]) - U(0, lams[0]) - U(1, lams[1])) / (KB * 300.0)
+    p = min(1.0, math.exp(delta))
+    zeros = np.zeros(2, np.int32)
+    n, acc = 4000, 0
+    for k in range(n):
+        ti, gr, vs, att, ac = oracle.exchange(cfg, 2 * k, zeros, zeros, np.zeros(2),
+                                              b["target_idx"], b["grid_rep"], E4)
+        acc += int(ac.sum())
+        assert att.sum() == 1 and np.all(vs == 1.0)
+        if ac.sum():
+            assert list(gr) == [1, 0] and ti[0, synth.DIM_H] == 1 and ti[1, synth.DIM_H] == 0
+    assert abs(acc / n - p) <= 4 * math.sqrt(max(p * (1 - p), 1e-12) / n) + 1.0 / n
+
+
+def test_hamiltonian_exchange_samples_the_pair_boltzmann_weights():
+    """Two frozen configurations (dt = 0) under repeated Hamiltonian exchange:
+    the arrangement (x_i at level 0, x_j at level 1) is held with probability
+    w_A / (w_A + w_B), w_A = exp(-[U_0(x_i) + U_1(x_j)] / kT) and w_B the
+    swapped arrangement, with the potentials from scaled parameters."""
+    lams = (1.0, 0.8)
+    b = _ham_pair((3, 4), lams, dt=0.0, mc_every=0, ex_every=1)
+    cfg, st, arr, keep = oracle.make_md(b, seed=23)
+    oracle.md_run(cfg, st, 0, 0, True)
+    x = [b["xyz"][b["atom_off"][r]:b["atom_off"][r + 1]] for r in (0, 1)]
+    U = lambda r, lam: _U_scaled(x[r], b, lam, r)[0]
+    beta = 1.0 / (KB * 300.0)
+    eA = -beta * (U(0, lams[0]) + U(1, lams[1]))
+    eB = -beta * (U(0, lams[1]) + U(1, lams[0]))
+    pA = 1.0 / (1.0 + math.exp(eB - eA))
+    n = 8000
+    held = np.empty(n)
+    for k in range(n):
+        oracle.md_run(cfg, st, k, 1, False)
+        held[k] = float(arr["target_idx"][synth.DIM_H] == 0)       # replica 0 at level 0
+    assert abs(held.mean() - pA) <= batch_mean_bound(held), (held.mean(), pA)
+
+
+def test_single_hamiltonian_level_equals_scaled_parameters():
+    """Dynamics with titration under U_l (one level, l = 0.7) follow the same
+    trajectory as dynamics at l = 1 with k_e and every epsilon_i multiplied
+    by 0.7: the forces, the titration energies and the Monte Carlo decisions
+    all see the scaled GB + Coulomb + LJ energy; the tether is not scaled."""
+    lam = 0.7
+    gs = oracle.obc2(k_e=332.0522173 * lam)
+    b = with_oracle_gref(synth.make_config(0, n_atoms=48, seed=71), gs)   # reference sites under U_l
+    b["mc_every"] = 2
+    bl = dict(b, H_scale=np.array([lam]))
+    bs = dict(b, eps=(lam * b["eps"].astype(np.float64)))
+    runs = []
+    for bb, gb in ((bl, None), (bs, gs)):
+        cfg, st, arr, keep = oracle.make_md(bb, gb=gb, seed=29)
+        oracle.md_run(cfg, st, 0, 30, True)
+        runs.append((arr["xyz"].copy(), arr["site_state"].copy(), arr["F"].copy(), arr["mc_acc"].copy()))
+    (x1, s1, f1, a1), (x2, s2, f2, a2) = runs
+    assert np.array_equal(s1, s2) and np.array_equal(a1, a2) and a1.sum() > 0
+    assert np.abs(x1 - x2).max() < 1e-9
+    assert np.abs(f1 - f2).max() < 1e-8 * np.abs(f2).max()
+
+
+def test_accepted_hamiltonian_swap_refreshes_the_forces():
+    """After an md_run step whose exchange swapped the Hamiltonians, each
+    replica's forces are those of its new level at its positions (the next
+    half kick must use them)."""
+    lams = (1.0, 0.9)
+    b = _ham_pair((1, 2), lams, ex_every=1, mc_every=0)     # this pair always accepts
+    cfg, st, arr, keep = oracle.make_md(b, seed=31)
+    oracle.md_run(cfg, st, 0, 1, True)
+    ti = arr["target_idx"].reshape(2, 4)
+    assert arr["ex_acc"].sum() == 1 and ti[0, synth.DIM_H] == 1
+    for r in (0, 1):
+        a0, a1 = b["atom_off"][r], b["atom_off"][r + 1]
+        x = arr["xyz"].reshape(-1, 3)[a0:a1]
+        _, g = _U_scaled(x, b, lams[ti[r, synth.DIM_H]], r)
+        F = arr["F"].reshape(-1, 3)[a0:a1]
+        assert np.abs(F + g).max() < 1e-10 * np.abs(g).max()
 
 
 # ------------------------------------------------ P13: dynamics
