@@ -339,9 +339,11 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     if ((rc = dev_alloc(&c->ex_vscale, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->ex_enb, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->ex_fscale, n_rep))) return done(rc);
+    if ((rc = dev_alloc(&c->mc_acc_fx, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->step, 2))) return done(rc);
     if ((rc = dev_alloc(&c->err, 1))) return done(rc);
     hipError_t e = hipMemset(c->err, 0, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(c->mc_acc_fx, 0, sizeof(int64_t) * n_rep);
     if (e == hipSuccess) e = hipMemset(c->step, 0, 2 * sizeof(uint64_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return done(hip_fail(e, "context init"));
@@ -369,6 +371,7 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     (void)hipFree(c->psi_fx); (void)hipFree(c->dEdR_fx); (void)hipFree(c->dEdR); (void)hipFree(c->chain_c);
     (void)hipFree(c->ke_fx); (void)hipFree(c->ex_nH); (void)hipFree(c->ex_ne); (void)hipFree(c->ex_eps);
     (void)hipFree(c->ex_vscale); (void)hipFree(c->ex_enb); (void)hipFree(c->ex_fscale);
+    (void)hipFree(c->mc_acc_fx);
     (void)hipFree(c->step); (void)hipFree(c->err);
     delete c;
     if (have_prev && prev != c_dev) (void)hipSetDevice(prev);

@@ -68,6 +68,7 @@ struct gbr_ctx {
     double* ex_enb = nullptr;        // [n_rep] unscaled GB + C + LJ energy
     float* ex_vscale = nullptr;
     double* ex_fscale = nullptr;     // [n_rep] force factor after Hamiltonian swaps
+    int64_t* mc_acc_fx = nullptr;    // [n_rep] titration attempt dE (2^32), zero between attempts
     uint64_t* step = nullptr;        // [2] current step index (second word unused)
     uint32_t* err = nullptr;         // device error word
     gbr::Timer timer;

@@ -144,10 +144,15 @@ __global__ void k_ke_out(int n_rep, const int64_t* __restrict__ ke_fx, double* _
 
 // ------------------------------------------------------------ titration
 // Electrostatic energy change of giving site `site` the charges of state
-// `nw`, at fixed Born radii, computed by one workgroup:
+// `nw`, at fixed Born radii:
 //   dE = sum_k d_k (K q)_k + 1/2 sum_{k,l} d_k d_l K_kl,   d = q_new - q on the site.
+// The sum over the replica's atoms j in (K q)_k is split into chunks of
+// TI_CHUNK atoms, one workgroup each (the quadratic term goes with chunk 0);
+// the chunk sums meet in a 64-bit fixed-point accumulator (2^32 per kcal/mol),
+// so the total does not depend on the order the workgroups finish in.
 constexpr int MAX_SITE = 64;
 constexpr int TB = 256;
+constexpr int TI_CHUNK = 2048;
 
 struct SiteSmem {
     float x[MAX_SITE], y[MAX_SITE], z[MAX_SITE], R[MAX_SITE], d[MAX_SITE], qn[MAX_SITE];
@@ -182,12 +187,14 @@ __device__ __forceinline__ float kg_of(float finv, float ketau, const Screening&
     return ketau * finv;
 }
 
-__device__ double site_delta_e(SiteSmem& sm, int m, int a0, int n, int ntot,
+// The part of dE from atoms j0 .. j1-1 (plus the quadratic term if quad),
+// summed over the workgroup; the result is valid in every thread.
+__device__ double site_delta_e(SiteSmem& sm, int m, int j0, int j1, bool quad_term, int ntot,
                                const float* __restrict__ xyz, const float* __restrict__ q,
                                const float* __restrict__ R, float ke_in, float ketau, Screening sc)
 {
     float lin = 0.0f;
-    for (int j = a0 + (int)threadIdx.x; j < a0 + n; j += blockDim.x) {
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) {
         const float xj = xyz[j], yj = xyz[ntot + j], zj = xyz[2 * ntot + j];
         const float qj = q[j], Rj = R[j];
         float acc = 0.0f;
@@ -208,7 +215,7 @@ __device__ double site_delta_e(SiteSmem& sm, int m, int a0, int n, int ntot,
         lin += acc * qj;
     }
     float quad = 0.0f;
-    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+    for (int t = threadIdx.x; quad_term && t < m * m; t += blockDim.x) {
         const int k = t / m, l = t % m;
         float K;
         if (k == l) {
@@ -242,120 +249,174 @@ __device__ void load_site(SiteSmem& sm, int m, int slot0, int nw, int ms, int nt
     __syncthreads();
 }
 
+// Candidate c = blockIdx.x is valid (a site in range, a state of that site,
+// at most MAX_SITE atoms); m and the replica are returned.
+__device__ bool candidate_ok(const gbr_sites& S, const int32_t* __restrict__ cand, int c, int n_rep,
+                             int& site, int& nw, int& m, int& rep) {
+    site = cand[2 * c];
+    nw = cand[2 * c + 1];
+    if (site < 0 || site >= S.n_sites) return false;
+    m = S.site_off[site + 1] - S.site_off[site];
+    rep = S.site_rep[site];
+    return nw >= 0 && nw < S.n_states[site] && m <= MAX_SITE && m >= 1 && rep >= 0 && rep < n_rep;
+}
+
+// Chunk blockIdx.y of candidate blockIdx.x, added into dE_fx[c] (fixed point).
 __global__ __launch_bounds__(TB) void k_titration(
     const int32_t* __restrict__ atom_off, int n_rep, int ntot, const float* __restrict__ xyz,
     const float* __restrict__ q, const float* __restrict__ R, gbr_sites S,
     const int32_t* __restrict__ cand, int n_cand, float ke_in, float ketau, Screening sc,
-    double* __restrict__ dE, uint32_t* __restrict__ err)
+    int64_t* __restrict__ dE_fx, uint32_t* __restrict__ err)
 {
     __shared__ SiteSmem sm;
     const int c = blockIdx.x;
     if (c >= n_cand) return;
-    const int site = cand[2 * c], nw = cand[2 * c + 1];
-    bool bad = site < 0 || site >= S.n_sites;
-    int m = 0, rep = 0;
-    if (!bad) {
-        m = S.site_off[site + 1] - S.site_off[site];
-        rep = S.site_rep[site];
-        bad = nw < 0 || nw >= S.n_states[site] || m > MAX_SITE || m < 1 || rep < 0 || rep >= n_rep;
-    }
-    if (bad) {
-        if (threadIdx.x == 0) {
-            raise_error(err, GBR_ERR_SITE);
-            dE[c] = __builtin_nan("");
-        }
-        return;
-    }
-    load_site(sm, m, S.site_off[site], nw, S.max_states, ntot, S.site_atoms, S.state_q, xyz, q, R);
+    int site, nw, m = 0, rep = 0;
+    if (!candidate_ok(S, cand, c, n_rep, site, nw, m, rep)) return;     // reported by k_titration_out
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
-    const double v = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau, sc);
-    if (threadIdx.x == 0) dE[c] = v;
+    const int j0 = (int)blockIdx.y * TI_CHUNK;
+    if (j0 >= n && blockIdx.y > 0) return;
+    load_site(sm, m, S.site_off[site], nw, S.max_states, ntot, S.site_atoms, S.state_q, xyz, q, R);
+    const double v = site_delta_e(sm, m, a0 + j0, a0 + min(n, j0 + TI_CHUNK), blockIdx.y == 0, ntot,
+                                  xyz, q, R, ke_in, ketau, sc);
+    if (threadIdx.x == 0) atomic_add_fx(&dE_fx[c], to_fixed(v, FX_ENERGY, err));
 }
 
-// One protonation attempt, then one redox attempt, for replica blockIdx.x.
+// dE[c] from its fixed-point sum (in place), or NaN and the site error bit for
+// an invalid candidate.
+__global__ void k_titration_out(int n_rep, gbr_sites S, const int32_t* __restrict__ cand,
+                                int n_cand, double* __restrict__ dE, uint32_t* __restrict__ err)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cand) return;
+    int site, nw, m = 0, rep = 0;
+    int64_t* fx = reinterpret_cast<int64_t*>(dE);
+    if (!candidate_ok(S, cand, c, n_rep, site, nw, m, rep)) {
+        raise_error(err, GBR_ERR_SITE);
+        dE[c] = __builtin_nan("");
+        return;
+    }
+    dE[c] = from_fixed(fx[c], INV_FX_ENERGY);
+}
+
+__global__ void k_zero_i64_n(int64_t* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Titration attempts, one site type at a time (protonation, then redox, so
+// that the redox attempt sees the charges the protonation attempt left):
+// k_mc_partial forms dE_elec of the replica's attempt chunk by chunk into
+// acc_fx[rep], k_mc_decide takes the Metropolis decision:
 //   dG = l dE - [G_ref(s') - G_ref(s)] + kT ln10 (pH - pKa_ref)(N_H(s') - N_H(s))   (pH)
 //   dG = l dE - [G_ref(s') - G_ref(s)] + F (E - E0_ref)(N_e(s') - N_e(s))            (redox)
-// (l: the replica's Hamiltonian scale)
-// accepted iff dG <= 0 or u < exp(-dG/kT); accepted charges are written before
-// the next attempt reads q.
-__global__ __launch_bounds__(TB) void k_mc(
+// (l: the replica's Hamiltonian scale) accepted iff dG <= 0 or u < exp(-dG/kT).
+// Both kernels draw the same Philox words: word 0 picks the site among the
+// replica's sites of the type, word 1 the new state, words 2-3 the uniform.
+struct McPick {
+    int site, nw;
+    U4 w;
+};
+
+__device__ McPick mc_pick(const gbr_sites& S, const int32_t* __restrict__ site_state, int rep,
+                          int type, uint64_t seed, uint64_t nstep) {
+    McPick p{-1, 0, U4{0, 0, 0, 0}};
+    const int s0 = S.rep_site_off[rep], s1 = S.rep_site_off[rep + 1];
+    int cnt = 0;
+    for (int k = s0; k < s1; ++k) cnt += S.site_type[k] == type;
+    if (cnt == 0) return p;
+    p.w = draw(seed, 0u, (uint32_t)rep, nstep, type == 0 ? STREAM_MCPH : STREAM_MCRED);
+    const uint32_t pick = choose(p.w.x, (uint32_t)cnt);
+    for (int k = s0, mm = 0; k < s1; ++k) {
+        if (S.site_type[k] != type) continue;
+        if ((uint32_t)mm == pick) { p.site = k; break; }
+        ++mm;
+    }
+    const int cur = site_state[p.site];
+    const uint32_t off = choose(p.w.y, (uint32_t)(S.n_states[p.site] - 1));
+    p.nw = (int)off < cur ? (int)off : (int)off + 1;
+    return p;
+}
+
+// Chunk blockIdx.y of replica blockIdx.x.
+__global__ __launch_bounds__(TB) void k_mc_partial(
     const int32_t* __restrict__ atom_off, int n_rep, int ntot, const uint64_t* __restrict__ step,
-    uint64_t seed, const float* __restrict__ xyz, float* __restrict__ q,
-    const float* __restrict__ R, gbr_sites S, gbr_grid G, int32_t* __restrict__ site_state,
-    const int32_t* __restrict__ target_idx, uint32_t* __restrict__ mc_stats, float ke_in,
-    float ketau, Screening sc, uint32_t* __restrict__ err)
+    uint64_t seed, int type, const float* __restrict__ xyz, const float* __restrict__ q,
+    const float* __restrict__ R, gbr_sites S, const int32_t* __restrict__ site_state, float ke_in,
+    float ketau, Screening sc, int64_t* __restrict__ acc_fx, uint32_t* __restrict__ err)
 {
     __shared__ SiteSmem sm;
-    __shared__ int s_site, s_new, s_acc;
+    __shared__ int s_site, s_new;
     const int rep = blockIdx.x;
     if (rep >= n_rep) return;
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
-    const uint64_t nstep = step[0];
-    const int ms = S.max_states;
-    for (int type = 0; type < 2; ++type) {
-        U4 w{0, 0, 0, 0};
-        if (threadIdx.x == 0) {
-            const int s0 = S.rep_site_off[rep], s1 = S.rep_site_off[rep + 1];
-            int cnt = 0;
-            for (int k = s0; k < s1; ++k) cnt += S.site_type[k] == type;
-            s_site = -1;
-            if (cnt > 0) {
-                w = draw(seed, 0u, (uint32_t)rep, nstep, type == 0 ? STREAM_MCPH : STREAM_MCRED);
-                const uint32_t pick = choose(w.x, (uint32_t)cnt);
-                int site = -1;
-                for (int k = s0, mm = 0; k < s1; ++k) {
-                    if (S.site_type[k] != type) continue;
-                    if ((uint32_t)mm == pick) { site = k; break; }
-                    ++mm;
-                }
-                const int cur = site_state[site];
-                const uint32_t off = choose(w.y, (uint32_t)(S.n_states[site] - 1));
-                s_new = (int)off < cur ? (int)off : (int)off + 1;
-                s_site = site;
-                if (S.site_off[site + 1] - S.site_off[site] > MAX_SITE) {
-                    raise_error(err, GBR_ERR_SITE);
-                    s_site = -1;
-                }
-            }
+    const int j0 = (int)blockIdx.y * TI_CHUNK;
+    if (j0 >= n && blockIdx.y > 0) return;
+    if (threadIdx.x == 0) {
+        const McPick p = mc_pick(S, site_state, rep, type, seed, step[0]);
+        const bool ok = p.site >= 0 && S.site_off[p.site + 1] - S.site_off[p.site] <= MAX_SITE;
+        s_site = ok ? p.site : -1;
+        s_new = p.nw;
+    }
+    __syncthreads();
+    const int site = s_site;
+    if (site < 0) return;                 // no site of the type, or reported by k_mc_decide
+    const int m = S.site_off[site + 1] - S.site_off[site];
+    load_site(sm, m, S.site_off[site], s_new, S.max_states, ntot, S.site_atoms, S.state_q, xyz, q, R);
+    const double v = site_delta_e(sm, m, a0 + j0, a0 + min(n, j0 + TI_CHUNK), blockIdx.y == 0, ntot,
+                                  xyz, q, R, ke_in, ketau, sc);
+    if (threadIdx.x == 0) atomic_add_fx(&acc_fx[rep], to_fixed(v, FX_ENERGY, err));
+}
+
+// One wavefront per replica: the decision, the new charges, the counters;
+// clears acc_fx[rep] for the next attempt.
+__global__ __launch_bounds__(64) void k_mc_decide(
+    int n_rep, const uint64_t* __restrict__ step, uint64_t seed, int type, float* __restrict__ q,
+    gbr_sites S, gbr_grid G, int32_t* __restrict__ site_state,
+    const int32_t* __restrict__ target_idx, uint32_t* __restrict__ mc_stats,
+    int64_t* __restrict__ acc_fx, uint32_t* __restrict__ err)
+{
+    const int rep = blockIdx.x;
+    if (rep >= n_rep) return;
+    const McPick p = mc_pick(S, site_state, rep, type, seed, step[0]);
+    if (p.site < 0) return;
+    const int site = p.site, nw = p.nw, ms = S.max_states;
+    const int m = S.site_off[site + 1] - S.site_off[site];
+    if (m > MAX_SITE) {
+        if (threadIdx.x == 0) raise_error(err, GBR_ERR_SITE);
+        return;
+    }
+    const int cur = site_state[site];
+    const double dEel = from_fixed(acc_fx[rep], INV_FX_ENERGY);
+    const int32_t* tg = target_idx + GBR_N_DIMS * rep;
+    const double kT = KB * G.T_vals[tg[GBR_DIM_T]];
+    const double lam = ham_scale(G.H_scale, target_idx, rep);
+    double dG = lam * dEel - (S.G_ref[site * ms + nw] - S.G_ref[site * ms + cur]);
+    if (type == 0) {
+        const double pH = G.pH_vals[tg[GBR_DIM_PH]];
+        dG += kT * LN10 * (pH - S.ref_value[site])
+              * (double)(S.state_nH[site * ms + nw] - S.state_nH[site * ms + cur]);
+    } else {
+        const double Ev = G.E_vals[tg[GBR_DIM_E]];
+        dG += FARADAY * (Ev - S.ref_value[site])
+              * (double)(S.state_ne[site * ms + nw] - S.state_ne[site * ms + cur]);
+    }
+    const double u = uniform53(p.w.z, p.w.w);
+    const bool acc = dG <= 0.0 || u < exp(-dG / kT);
+    __syncthreads();                      // every lane has read site_state and acc_fx
+    if (acc) {
+        const int slot0 = S.site_off[site];
+        for (int k = threadIdx.x; k < m; k += blockDim.x)
+            q[S.site_atoms[slot0 + k]] = S.state_q[(int64_t)(slot0 + k) * ms + nw];
+    }
+    if (threadIdx.x == 0) {
+        if (!(dG == dG)) raise_error(err, GBR_ERR_NONFINITE);
+        if (acc) site_state[site] = nw;
+        acc_fx[rep] = 0;
+        if (mc_stats) {
+            mc_stats[2 * site] += 1;
+            if (acc) mc_stats[2 * site + 1] += 1;
         }
-        __syncthreads();
-        const int site = s_site;
-        if (site < 0) { __syncthreads(); continue; }
-        const int nw = s_new;
-        const int m = S.site_off[site + 1] - S.site_off[site];
-        load_site(sm, m, S.site_off[site], nw, ms, ntot, S.site_atoms, S.state_q, xyz, q, R);
-        const double dEel = site_delta_e(sm, m, a0, n, ntot, xyz, q, R, ke_in, ketau, sc);
-        if (threadIdx.x == 0) {
-            const int cur = site_state[site];
-            const int32_t* tg = target_idx + GBR_N_DIMS * rep;
-            const double T = G.T_vals[tg[GBR_DIM_T]];
-            const double kT = KB * T;
-            const double lam = ham_scale(G.H_scale, target_idx, rep);
-            double dG = lam * dEel - (S.G_ref[site * ms + nw] - S.G_ref[site * ms + cur]);
-            if (type == 0) {
-                const double pH = G.pH_vals[tg[GBR_DIM_PH]];
-                dG += kT * LN10 * (pH - S.ref_value[site])
-                      * (double)(S.state_nH[site * ms + nw] - S.state_nH[site * ms + cur]);
-            } else {
-                const double Ev = G.E_vals[tg[GBR_DIM_E]];
-                dG += FARADAY * (Ev - S.ref_value[site])
-                      * (double)(S.state_ne[site * ms + nw] - S.state_ne[site * ms + cur]);
-            }
-            const double u = uniform53(w.z, w.w);
-            const bool acc = dG <= 0.0 || u < exp(-dG / kT);
-            if (!(dG == dG)) raise_error(err, GBR_ERR_NONFINITE);
-            s_acc = acc ? 1 : 0;
-            if (acc) site_state[site] = nw;
-            if (mc_stats) {
-                mc_stats[2 * site] += 1;
-                if (acc) mc_stats[2 * site + 1] += 1;
-            }
-        }
-        __syncthreads();
-        if (s_acc)
-            for (int k = threadIdx.x; k < m; k += blockDim.x) q[sm.atom[k]] = sm.qn[k];
-        __threadfence_block();
-        __syncthreads();
     }
 }
 
@@ -560,12 +621,20 @@ Screening make_screening(const gbr_gb_params& p) {
     return sc;
 }
 
+static int ti_chunks(const gbr_ctx* c) { return (c->max_n + TI_CHUNK - 1) / TI_CHUNK; }
+
 hipError_t launch_mc(const gbr_ctx* c, const MDArgs& a, hipStream_t s) {
     const GBConstH k = make_const(c->prm);
-    hipLaunchKernelGGL(k_mc, dim3(c->n_rep), dim3(TB), 0, s, c->atom_off, c->n_rep, c->n_atoms,
-                       c->step, a.seed, a.st.xyz, a.st.q, a.st.R, a.pr.sites, a.pr.grid,
-                       a.st.site_state, a.st.target_idx, a.st.mc_stats, k.ke_in,
-                       (float)(k.ke_d * k.tau_d), make_screening(c->prm), c->err);
+    const dim3 grid(c->n_rep, ti_chunks(c));
+    for (int type = 0; type < 2; ++type) {
+        hipLaunchKernelGGL(k_mc_partial, grid, dim3(TB), 0, s, c->atom_off, c->n_rep, c->n_atoms,
+                           c->step, a.seed, type, a.st.xyz, a.st.q, a.st.R, a.pr.sites,
+                           a.st.site_state, k.ke_in, (float)(k.ke_d * k.tau_d),
+                           make_screening(c->prm), c->mc_acc_fx, c->err);
+        hipLaunchKernelGGL(k_mc_decide, dim3(c->n_rep), dim3(64), 0, s, c->n_rep, c->step, a.seed,
+                           type, a.st.q, a.pr.sites, a.pr.grid, a.st.site_state, a.st.target_idx,
+                           a.st.mc_stats, c->mc_acc_fx, c->err);
+    }
     return hipGetLastError();
 }
 
@@ -574,9 +643,13 @@ hipError_t launch_titration(const gbr_ctx* c, const float* xyz, const float* q, 
                             double* dE, hipStream_t s) {
     if (n_cand <= 0) return hipSuccess;
     const GBConstH k = make_const(c->prm);
-    hipLaunchKernelGGL(k_titration, dim3(n_cand), dim3(TB), 0, s, c->atom_off, c->n_rep,
+    int64_t* fx = reinterpret_cast<int64_t*>(dE);
+    hipLaunchKernelGGL(k_zero_i64_n, dim3((n_cand + 255) / 256), dim3(256), 0, s, fx, n_cand);
+    hipLaunchKernelGGL(k_titration, dim3(n_cand, ti_chunks(c)), dim3(TB), 0, s, c->atom_off, c->n_rep,
                        c->n_atoms, xyz, q, R, sites, cand, n_cand, k.ke_in,
-                       (float)(k.ke_d * k.tau_d), make_screening(c->prm), dE, c->err);
+                       (float)(k.ke_d * k.tau_d), make_screening(c->prm), fx, c->err);
+    hipLaunchKernelGGL(k_titration_out, dim3((n_cand + 255) / 256), dim3(256), 0, s, c->n_rep, sites,
+                       cand, n_cand, dE, c->err);
     return hipGetLastError();
 }
 

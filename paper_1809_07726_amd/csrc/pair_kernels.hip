@@ -681,46 +681,73 @@ __global__ __launch_bounds__(256) void k_tile_boxes(
     }
 }
 
-// One thread per item of a list: block items whose I block (NI tiles) and J
-// tile boxes are farther apart than rc are dropped, the rest (and every
-// triangle or diagonal item) appended to the culled list, one atomic per
-// wavefront.  The culled order is arbitrary; the fixed-point sums do not
-// depend on it.
+// Culling of a list: block items whose I block (NI tiles) and J tile boxes
+// are farther apart than rc are dropped, the rest (and every triangle or
+// diagonal item) appended to the culled list.  A workgroup takes CULL_ROUNDS
+// rounds of 256 consecutive items, keeps their survivors in list order and
+// reserves its output range with one atomic; the workgroups' ranges land in
+// arbitrary order, which the fixed-point sums do not depend on.
+constexpr int CULL_ROUNDS = 8;
+
+__device__ __forceinline__ bool cull_keep(int2 wi, int ni, const int32_t* __restrict__ atom_off,
+                                          const int32_t* __restrict__ tile_base,
+                                          const float4* __restrict__ box, float rc2) {
+    if (((unsigned)wi.x >> 30) != (unsigned)ITEM_BLOCK) return true;
+    const int rep = wi.x & 0x3FFFFFF;
+    const int A = wi.y >> 16, B = wi.y & 0xFFFF;
+    const int T = (atom_off[rep + 1] - atom_off[rep] + 63) >> 6;
+    const int tb = tile_base[rep];
+    float4 ilo = box[2 * (tb + A * ni)], ihi = box[2 * (tb + A * ni) + 1];
+    for (int u = 1; u < ni && A * ni + u < T; ++u) {
+        const float4 l = box[2 * (tb + A * ni + u)], h = box[2 * (tb + A * ni + u) + 1];
+        ilo = make_float4(fminf(ilo.x, l.x), fminf(ilo.y, l.y), fminf(ilo.z, l.z), 0.0f);
+        ihi = make_float4(fmaxf(ihi.x, h.x), fmaxf(ihi.y, h.y), fmaxf(ihi.z, h.z), 0.0f);
+    }
+    const float4 jlo = box[2 * (tb + B)], jhi = box[2 * (tb + B) + 1];
+    const float dx = fmaxf(0.0f, fmaxf(ilo.x - jhi.x, jlo.x - ihi.x));
+    const float dy = fmaxf(0.0f, fmaxf(ilo.y - jhi.y, jlo.y - ihi.y));
+    const float dz = fmaxf(0.0f, fmaxf(ilo.z - jhi.z, jlo.z - ihi.z));
+    return dx * dx + dy * dy + dz * dz < rc2;
+}
+
 __global__ __launch_bounds__(256) void k_cull(
     const int2* __restrict__ items, int n_items, int ni, const int32_t* __restrict__ atom_off,
     const int32_t* __restrict__ tile_base, const float4* __restrict__ box, float rc2,
     int2* __restrict__ out, int32_t* __restrict__ count)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    bool keep = false;
-    int2 wi = make_int2(0, 0);
-    if (i < n_items) {
-        wi = items[i];
-        keep = true;
-        if (((unsigned)wi.x >> 30) == (unsigned)ITEM_BLOCK) {
-            const int rep = wi.x & 0x3FFFFFF;
-            const int A = wi.y >> 16, B = wi.y & 0xFFFF;
-            const int T = (atom_off[rep + 1] - atom_off[rep] + 63) >> 6;
-            const int tb = tile_base[rep];
-            float4 ilo = box[2 * (tb + A * ni)], ihi = box[2 * (tb + A * ni) + 1];
-            for (int u = 1; u < ni && A * ni + u < T; ++u) {
-                const float4 l = box[2 * (tb + A * ni + u)], h = box[2 * (tb + A * ni + u) + 1];
-                ilo = make_float4(fminf(ilo.x, l.x), fminf(ilo.y, l.y), fminf(ilo.z, l.z), 0.0f);
-                ihi = make_float4(fmaxf(ihi.x, h.x), fmaxf(ihi.y, h.y), fmaxf(ihi.z, h.z), 0.0f);
-            }
-            const float4 jlo = box[2 * (tb + B)], jhi = box[2 * (tb + B) + 1];
-            const float dx = fmaxf(0.0f, fmaxf(ilo.x - jhi.x, jlo.x - ihi.x));
-            const float dy = fmaxf(0.0f, fmaxf(ilo.y - jhi.y, jlo.y - ihi.y));
-            const float dz = fmaxf(0.0f, fmaxf(ilo.z - jhi.z, jlo.z - ihi.z));
-            keep = dx * dx + dy * dy + dz * dz < rc2;
+    __shared__ int s_cnt[CULL_ROUNDS * 4];
+    __shared__ int s_base;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long first = (long long)blockIdx.x * (256 * CULL_ROUNDS);
+    int2 wi[CULL_ROUNDS];
+    unsigned long long m[CULL_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < CULL_ROUNDS; ++r) {
+        const long long i = first + r * 256 + threadIdx.x;
+        bool keep = false;
+        wi[r] = make_int2(0, 0);
+        if (i < n_items) {
+            wi[r] = items[i];
+            keep = cull_keep(wi[r], ni, atom_off, tile_base, box, rc2);
         }
+        m[r] = __ballot(keep);
+        if (lane == 0) s_cnt[r * 4 + w] = __popcll(m[r]);
     }
-    const unsigned long long m = __ballot(keep);
-    int base = 0;
-    if (lane == 0 && m) base = atomicAdd(count, __popcll(m));
-    base = __shfl(base, 0, 64);
-    if (keep) out[base + __popcll(m & ((1ull << lane) - 1ull))] = wi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int k = 0; k < CULL_ROUNDS * 4; ++k) {   // exclusive prefix in list order
+            const int c = s_cnt[k];
+            s_cnt[k] = total;
+            total += c;
+        }
+        s_base = total ? atomicAdd(count, total) : 0;
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int r = 0; r < CULL_ROUNDS; ++r)
+        if ((m[r] >> lane) & 1ull) out[s_base + s_cnt[r * 4 + w] + __popcll(m[r] & below)] = wi[r];
 }
 
 int grid_for(const gbr_ctx* c, int n_items) {
@@ -782,7 +809,8 @@ hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s) {
         done[idx][kind[k]] = true;
         const PairList& L = c->lists[idx];
         if (L.n_items == 0) continue;
-        hipLaunchKernelGGL(k_cull, dim3((L.n_items + 255) / 256), dim3(256), 0, s, L.items, L.n_items, L.ni,
+        const int per_group = 256 * CULL_ROUNDS;
+        hipLaunchKernelGGL(k_cull, dim3((L.n_items + per_group - 1) / per_group), dim3(256), 0, s, L.items, L.n_items, L.ni,
                            c->atom_off, c->tile_base, c->tile_box, (float)(rc[kind[k]] * rc[kind[k]]),
                            L.culled[kind[k]], L.n_culled[kind[k]]);
     }

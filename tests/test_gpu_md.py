@@ -77,6 +77,29 @@ def test_md_step_matches_oracle_trajectory():
     assert g[-1]["mc_stats"][0::2].sum() == o[-1]["mc_att"].sum() == 4
 
 
+def test_md_step_titration_on_a_replica_of_several_chunks_matches_oracle():
+    """A 2,500-atom replica (its titration sums span two chunks of atoms):
+    attempts every step for 6 steps follow the oracle's states exactly.  G_ref
+    is the sites' energy change in the whole system at the start, so that the
+    attempts are accepted about half of the time."""
+    b = synth.make_config(0, n_atoms=2500, seed=1010)
+    b["mc_every"] = 1
+    _, R, _ = oracle.born(b["xyz"], b["rho"], b["screen"])
+    ms = b["max_states"]
+    for s in range(b["n_sites"]):
+        sl = slice(b["site_off"][s], b["site_off"][s + 1])
+        qn = b["state_q"].reshape(-1, ms)[sl, 1]
+        b["G_ref"][s * ms + 1] = oracle.delta_e(b["xyz"], b["q"], R, b["site_atoms"][sl], qn)
+    g = _gpu_md(b, 2300, [3, 3])
+    o = _oracle_md(b, 2300, [3, 3])
+    for gs, os_ in zip(g, o):
+        assert np.array_equal(gs["site_state"], os_["site_state"])
+        assert np.allclose(gs["q"], os_["q"], atol=1e-6)
+        assert np.abs(gs["xyz"] - os_["xyz"].reshape(-1, 3)).max() < 1e-4
+    assert g[-1]["mc_stats"][0::2].sum() == o[-1]["mc_att"].sum() == 12
+    assert o[-1]["mc_acc"].sum() > 0
+
+
 def test_md_first_step_is_exact_to_fp32():
     """One step from rest: the Ornstein-Uhlenbeck noise is the same Philox
     stream on both sides, so positions agree to FP32 rounding."""

@@ -97,11 +97,15 @@ def test_bitwise_reproducible_and_newton_balanced():
         assert np.abs(F.sum(0)).max() <= 2e-8 * np.abs(F).sum()
 
 
-def test_titration_delta_e_matches_oracle():
+@pytest.mark.parametrize("n_atoms,n_rep", [(None, 4), (5000, 2)])
+def test_titration_delta_e_matches_oracle(n_atoms, n_rep):
+    """Every site's state-1 candidate against the oracle's direct difference;
+    5,000-atom replicas split the sum over the replica's atoms into three
+    chunks."""
     from paper_1809_07726_amd.gb import Context
     from gpu_common import to_dev
     import torch
-    b = synth.make_config(1, n_rep=4, per_replica_jitter=True)
+    b = synth.make_config(1, n_atoms=n_atoms, n_rep=n_rep, per_replica_jitter=True)
     d = to_dev(b)
     ctx = Context(b["atom_off"])
     t = d.t
