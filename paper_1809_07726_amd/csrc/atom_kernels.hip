@@ -60,33 +60,46 @@ __global__ __launch_bounds__(256) void k_coef(
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint64_t* __restrict__ step,
     uint32_t* __restrict__ err)
 {
-    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
-    if (t >= n_tiles) return;
+    const int w = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     const int lane = threadIdx.x & 63;
     // inside md_step: the step counter advances here, once per step (nothing in
     // this kernel reads it; the next step's kernels and the exchange do)
-    if (step && t == 0 && lane == 0) step[0] = step[0] + 1;
-    const int2 tl = tiles[t];
-    const int a0 = atom_off[tl.x], n = atom_off[tl.x + 1] - a0;
-    const int li = tl.y * 64 + lane;
-    double eself = 0.0;
-    if (li < n) {
-        const int a = a0 + li;
-        const double qa = q[a], Ra = R[a];
-        double kg = ketau / Ra, dkg = -ketau / (Ra * Ra);
-        if (kappa > 0.0) {
-            const double es = exp(-kappa * Ra);
-            kg = (ketau + keout * (1.0 - es)) / Ra;
-            dkg = -kg / Ra + keout * kappa * es / Ra;
+    if (step && w == 0 && lane == 0) step[0] = step[0] + 1;
+    // TILES_PER_WAVE consecutive tiles per wavefront; the self energies of
+    // those in one replica go out in one atomic
+    int cur = -1;
+    long long esum = 0;
+    for (int i = 0; i < TILES_PER_WAVE; ++i) {
+        const int t = w * TILES_PER_WAVE + i;
+        if (t >= n_tiles) break;
+        const int2 tl = tiles[t];
+        const int a0 = atom_off[tl.x], n = atom_off[tl.x + 1] - a0;
+        const int li = tl.y * 64 + lane;
+        double eself = 0.0;
+        if (li < n) {
+            const int a = a0 + li;
+            const double qa = q[a], Ra = R[a];
+            double kg = ketau / Ra, dkg = -ketau / (Ra * Ra);
+            if (kappa > 0.0) {
+                const double es = exp(-kappa * Ra);
+                kg = (ketau + keout * (1.0 - es)) / Ra;
+                dkg = -kg / Ra + keout * kappa * es / Ra;
+            }
+            const double g = from_fixed(dEdR_fx[a], INV_FX_FORCE) - 0.5 * qa * qa * dkg;
+            dEdR[a] = g;
+            cc[a] = (float)(g * (double)dRdpsi[a] * 0.5 * ((double)rho[a] - offset));
+            eself = -0.5 * qa * qa * kg;
+            if (dEdq_fx) dEdq_fx[a] += to_fixed(-qa * kg, FX_FORCE, err);
         }
-        const double g = from_fixed(dEdR_fx[a], INV_FX_FORCE) - 0.5 * qa * qa * dkg;
-        dEdR[a] = g;
-        cc[a] = (float)(g * (double)dRdpsi[a] * 0.5 * ((double)rho[a] - offset));
-        eself = -0.5 * qa * qa * kg;
-        if (dEdq_fx) dEdq_fx[a] += to_fixed(-qa * kg, FX_FORCE, err);
+        const long long fx = to_fixed(wave_sum_d(eself), FX_ENERGY, err);
+        if (tl.x != cur) {
+            if (cur >= 0 && lane == 0) atomic_add_fx(&energy_fx[4 * cur], esum);
+            cur = tl.x;
+            esum = 0;
+        }
+        esum += fx;
     }
-    const double s = wave_sum_d(eself);
-    if (lane == 0) atomic_add_fx(&energy_fx[4 * tl.x], to_fixed(s, FX_ENERGY, err));
+    if (cur >= 0 && lane == 0) atomic_add_fx(&energy_fx[4 * cur], esum);
 }
 
 // per-atom part of dE/drho_i: dE/dR_i [R^2 (1/rho~^2 - tanh/rho^2) + dR/dpsi * psi/rho~]
@@ -176,7 +189,8 @@ hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const
                        const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, uint64_t* step,
                        hipStream_t s) {
     const GBConstH k = make_const(c->prm);
-    hipLaunchKernelGGL(k_coef, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
+    const int waves = (c->n_tiles + TILES_PER_WAVE - 1) / TILES_PER_WAVE;
+    hipLaunchKernelGGL(k_coef, dim3((waves + 3) / 4), dim3(256), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, q, rho, R, dRdpsi, c->dEdR_fx, k.ke_d * k.tau_d,
                        c->prm.k_e / c->prm.eps_out, c->prm.kappa, c->prm.offset,
                        c->dEdR, c->chain_c, energy_fx, dEdq_fx, step, c->err);

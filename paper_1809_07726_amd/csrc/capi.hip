@@ -319,11 +319,40 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
         if ((rc = upload(c->tile_base, tb.data(), sizeof(int32_t) * n_rep))) return done(rc);
         if ((rc = dev_alloc(&c->tile_box, 2 * (size_t)c->n_tiles))) return done(rc);
         if ((rc = dev_alloc(&c->cull_count, 8))) return done(rc);
-        for (int k = 0; k < 4; ++k)
+        std::vector<gbr::PairItem> intra, iblocks;
+        std::vector<int32_t> p0;
+        std::vector<gbr::PackWindow> wins;
+        static_assert(sizeof(gbr::PackWindow) == sizeof(int4), "window layout");
+        for (int k = 0; k < 4; ++k) {
+            gbr::PairList& L = c->lists[k];
+            gbr::build_pair_items(c->h_atom_off.data(), n_rep, nis[k], items);
+            int64_t cap = 0;
+            gbr::build_packed_parts(c->h_atom_off.data(), n_rep, nis[k], items, intra, iblocks, p0, wins, cap);
+            if ((int64_t)intra.size() + cap > 0x7FFFFFFF || cap * 64 > 0x7FFFFFFF)
+                return done(fail(GBR_E_INVAL, "work list too long"));
+            L.n_intra = (int32_t)intra.size();
+            L.n_iblk = (int32_t)iblocks.size();
+            L.n_win = (int32_t)wins.size();
+            L.pk_cap = cap;
+            if ((rc = dev_alloc(&L.iblk, iblocks.size()))) return done(rc);
+            if (!iblocks.empty() && (rc = upload(L.iblk, iblocks.data(), sizeof(int2) * iblocks.size())))
+                return done(rc);
+            if ((rc = dev_alloc(&L.blk_p0, p0.size()))) return done(rc);
+            if (!p0.empty() && (rc = upload(L.blk_p0, p0.data(), sizeof(int32_t) * p0.size()))) return done(rc);
+            if ((rc = dev_alloc(&L.win, wins.size()))) return done(rc);
+            if (!wins.empty() && (rc = upload(L.win, wins.data(), sizeof(int4) * wins.size()))) return done(rc);
             for (int v = 0; v < 2; ++v) {
-                if ((rc = dev_alloc(&c->lists[k].culled[v], (size_t)c->lists[k].n_items))) return done(rc);
-                c->lists[k].n_culled[v] = c->cull_count + 2 * k + v;
+                if ((rc = dev_alloc(&L.blk_count[v], iblocks.size()))) return done(rc);
+                if (hipMemset(L.blk_count[v], 0, sizeof(int32_t) * std::max<size_t>(iblocks.size(), 1)) != hipSuccess)
+                    return done(fail(GBR_E_HIP, "clearing the packing counts"));
+                if ((rc = dev_alloc(&L.culled[v], (size_t)(L.n_intra + cap)))) return done(rc);
+                if (!intra.empty() && (rc = upload(L.culled[v], intra.data(), sizeof(int2) * intra.size())))
+                    return done(rc);
+                if ((rc = dev_alloc(&L.pk_hdr[v], std::max<size_t>((size_t)cap, 1)))) return done(rc);
+                if ((rc = dev_alloc(&L.pk_j[v], std::max<size_t>((size_t)cap * 64, 1)))) return done(rc);
+                L.n_culled[v] = c->cull_count + 2 * k + v;
             }
+        }
     }
     // default register blocking: more i atoms per lane for larger replicas
     const int ni = max_n >= 4096 ? 8 : (max_n >= 512 ? 4 : (max_n >= 128 ? 2 : 1));
@@ -364,7 +393,13 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     for (auto& ev : c->timer.pool) if (ev) (void)hipEventDestroy(ev);
     (void)hipFree(c->atom_off);
     (void)hipFree(c->tiles);
-    for (auto& L : c->lists) { (void)hipFree(L.items); (void)hipFree(L.culled[0]); (void)hipFree(L.culled[1]); }
+    for (auto& L : c->lists) {
+        (void)hipFree(L.items); (void)hipFree(L.iblk); (void)hipFree(L.blk_p0); (void)hipFree(L.win);
+        for (int v = 0; v < 2; ++v) {
+            (void)hipFree(L.culled[v]); (void)hipFree(L.blk_count[v]); (void)hipFree(L.pk_hdr[v]);
+            (void)hipFree(L.pk_j[v]);
+        }
+    }
     (void)hipFree(c->tile_base);
     (void)hipFree(c->tile_box);
     (void)hipFree(c->cull_count);

@@ -27,6 +27,10 @@ constexpr float FXF_ENERGY = 4294967296.0f;
 
 enum Stream : uint32_t { STREAM_O = 1, STREAM_MCPH = 2, STREAM_MCRED = 3, STREAM_EX = 4 };
 
+// Per-tile kernels that sum per-replica energies take this many consecutive
+// tiles per wavefront and send one atomic per replica they meet.
+constexpr int TILES_PER_WAVE = 4;
+
 // ------------------------------------------------------------ fixed point
 __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t bits) {
     __hip_atomic_fetch_or(err, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -17,10 +17,22 @@ struct PairList {
     int ni = 0;                // i atoms per lane the list was built for
     int2* items = nullptr;     // {rep | type << 30, (A << 16) | B}
     int32_t n_items = 0;
-    // with both cutoffs: the items whose tiles come within reach, for the
-    // descreening passes (rgbmax, [0]) and for the energy pass (cut, [1])
+    // with both cutoffs: the lists the passes run, for the descreening passes
+    // (radius rgbmax, [0]) and for the energy pass (cut, [1]): the n_intra
+    // items whose pairs lie inside one I block (a fixed prefix), then the
+    // packed items of the current positions
     int2* culled[2] = {nullptr, nullptr};
     int32_t* n_culled[2] = {nullptr, nullptr};   // their counts (device)
+    int32_t n_intra = 0;
+    int2* iblk = nullptr;                        // I blocks {rep, A} with tiles after them
+    int32_t* blk_p0 = nullptr;                   // [n_iblk] each block's first packed tile
+    int32_t n_iblk = 0;
+    int4* win = nullptr;                         // packing windows (pair_list.h PackWindow)
+    int32_t n_win = 0;
+    int64_t pk_cap = 0;                          // packed tiles at most (tiles after each block)
+    int32_t* blk_count[2] = {nullptr, nullptr};  // [n_iblk] atoms packed, zero between evaluations
+    int32_t* pk_hdr[2] = {nullptr, nullptr};     // [pk_cap] A << 7 | nj
+    int32_t* pk_j[2] = {nullptr, nullptr};       // [64 pk_cap] replica-local J atoms
 };
 
 struct LaunchShape {
@@ -53,7 +65,7 @@ struct gbr_ctx {
     bool cull = false;               // both cutoffs set: the pair passes run culled lists
     int32_t* tile_base = nullptr;    // [n_rep] index of each replica's first tile
     float4* tile_box = nullptr;      // [2 n_tiles] per-tile bounding boxes (min, max)
-    int32_t* cull_count = nullptr;   // [8] survivors per list and radius
+    int32_t* cull_count = nullptr;   // [8] items per list and radius
     int ni_born = 4, ni_energy = 4, ni_chain = 4;
     gbr::LaunchShape shape;
     // workspace
@@ -103,9 +115,9 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
                              hipStream_t s, LaunchEvents ev = {});
 
 // With both cutoffs: per-tile bounding boxes of xyz, then for every list in
-// use the block items whose I block and J tile come within rgbmax (for the
-// descreening passes) or cut (for the energy pass), and every triangle or
-// diagonal item, compacted into that list's culled copies.
+// use and every I block the atoms after the block that come within rgbmax
+// (for the descreening passes) or cut (for the energy pass) of its box,
+// packed into items after the list's intra-block items.
 hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s);
 
 // per-atom kernels ------------------------------------------------------------

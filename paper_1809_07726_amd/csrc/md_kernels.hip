@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_md_first(
 
 // The pair forces scaled by the replica's Hamiltonian scale, plus the tether
 // k |x - x0|^2 (its energy in the replica's slot 3); then (kick) v += dt/2 F/m
-// and the kinetic energy.
+// and the kinetic energy.  TILES_PER_WAVE tiles per wavefront.
 __global__ __launch_bounds__(256) void k_md_last(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
     int ntot, double hdt, double k_t, const double* __restrict__ H_scale,
@@ -103,38 +103,54 @@ __global__ __launch_bounds__(256) void k_md_last(
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx,
     int kick, uint32_t* __restrict__ err)
 {
-    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
-    if (t >= n_tiles) return;
+    const int w = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     const int lane = threadIdx.x & 63;
-    const int2 tl = tiles[t];
-    const int rep = tl.x;
-    const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
-    const int li = tl.y * 64 + lane;
-    double et = 0.0, kin = 0.0;
-    if (li < n) {
-        const int a = a0 + li;
-        const double m = mass[a], im = ACC_CONV / m;
-        const double lam = ham_scale(H_scale, target_idx, rep);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int64_t idx = (int64_t)d * ntot + a;
-            const double dx = (double)xyz[idx] - (double)x0[idx];
-            et += k_t * dx * dx;
-            const int64_t f = scale_fx(force_fx[idx], lam, err) + to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
-            force_fx[idx] = f;
-            double vv = v[idx];
-            if (kick) {
-                vv += hdt * from_fixed(f, INV_FX_FORCE) * im;
-                v[idx] = (float)vv;
-            }
-            kin += 0.5 * m * (double)(float)vv * (double)(float)vv / ACC_CONV;
+    int cur = -1;
+    long long se_sum = 0, sk_sum = 0;
+    auto flush = [&]() {
+        if (cur >= 0 && lane == 0) {
+            atomic_add_fx(&energy_fx[4 * cur + 3], se_sum);
+            atomic_add_fx(&ke_fx[cur], sk_sum);
         }
+        se_sum = sk_sum = 0;
+    };
+    for (int i = 0; i < TILES_PER_WAVE; ++i) {
+        const int t = w * TILES_PER_WAVE + i;
+        if (t >= n_tiles) break;
+        const int2 tl = tiles[t];
+        const int rep = tl.x;
+        const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
+        const int li = tl.y * 64 + lane;
+        double et = 0.0, kin = 0.0;
+        if (li < n) {
+            const int a = a0 + li;
+            const double m = mass[a], im = ACC_CONV / m;
+            const double lam = ham_scale(H_scale, target_idx, rep);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int64_t idx = (int64_t)d * ntot + a;
+                const double dx = (double)xyz[idx] - (double)x0[idx];
+                et += k_t * dx * dx;
+                const int64_t f = scale_fx(force_fx[idx], lam, err) + to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
+                force_fx[idx] = f;
+                double vv = v[idx];
+                if (kick) {
+                    vv += hdt * from_fixed(f, INV_FX_FORCE) * im;
+                    v[idx] = (float)vv;
+                }
+                kin += 0.5 * m * (double)(float)vv * (double)(float)vv / ACC_CONV;
+            }
+        }
+        const long long se = to_fixed(wave_sum_d(et), FX_ENERGY, err);
+        const long long sk = to_fixed(wave_sum_d(kin), FX_ENERGY, err);
+        if (rep != cur) {
+            flush();
+            cur = rep;
+        }
+        se_sum += se;
+        sk_sum += sk;
     }
-    const double se = wave_sum_d(et), sk = wave_sum_d(kin);
-    if (lane == 0) {
-        atomic_add_fx(&energy_fx[4 * rep + 3], to_fixed(se, FX_ENERGY, err));
-        atomic_add_fx(&ke_fx[rep], to_fixed(sk, FX_ENERGY, err));
-    }
+    flush();
 }
 
 __global__ void k_ke_out(int n_rep, const int64_t* __restrict__ ke_fx, double* __restrict__ ke) {
@@ -318,19 +334,33 @@ struct McPick {
     U4 w;
 };
 
+// Called by all 64 lanes of one wavefront (the result is the same in every
+// lane): the replica's sites are scanned 64 at a time.
 __device__ McPick mc_pick(const gbr_sites& S, const int32_t* __restrict__ site_state, int rep,
                           int type, uint64_t seed, uint64_t nstep) {
     McPick p{-1, 0, U4{0, 0, 0, 0}};
+    const int lane = threadIdx.x & 63;
     const int s0 = S.rep_site_off[rep], s1 = S.rep_site_off[rep + 1];
     int cnt = 0;
-    for (int k = s0; k < s1; ++k) cnt += S.site_type[k] == type;
+    for (int k0 = s0; k0 < s1; k0 += 64) {
+        const int k = k0 + lane;
+        cnt += __popcll(__ballot(k < s1 && S.site_type[k] == type));
+    }
     if (cnt == 0) return p;
     p.w = draw(seed, 0u, (uint32_t)rep, nstep, type == 0 ? STREAM_MCPH : STREAM_MCRED);
-    const uint32_t pick = choose(p.w.x, (uint32_t)cnt);
-    for (int k = s0, mm = 0; k < s1; ++k) {
-        if (S.site_type[k] != type) continue;
-        if ((uint32_t)mm == pick) { p.site = k; break; }
-        ++mm;
+    const int pick = (int)choose(p.w.x, (uint32_t)cnt);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int k0 = s0, seen = 0; k0 < s1; k0 += 64) {
+        const int k = k0 + lane;
+        const bool mine = k < s1 && S.site_type[k] == type;
+        const unsigned long long b = __ballot(mine);
+        const int c = __popcll(b);
+        if (pick < seen + c) {                 // the (pick - seen)-th site of this window
+            const unsigned long long hit = __ballot(mine && __popcll(b & below) == pick - seen);
+            p.site = k0 + __ffsll((long long)hit) - 1;
+            break;
+        }
+        seen += c;
     }
     const int cur = site_state[p.site];
     const uint32_t off = choose(p.w.y, (uint32_t)(S.n_states[p.site] - 1));
@@ -352,11 +382,13 @@ __global__ __launch_bounds__(TB) void k_mc_partial(
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
     const int j0 = (int)blockIdx.y * TI_CHUNK;
     if (j0 >= n && blockIdx.y > 0) return;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {                 // wavefront 0 picks
         const McPick p = mc_pick(S, site_state, rep, type, seed, step[0]);
-        const bool ok = p.site >= 0 && S.site_off[p.site + 1] - S.site_off[p.site] <= MAX_SITE;
-        s_site = ok ? p.site : -1;
-        s_new = p.nw;
+        if (threadIdx.x == 0) {
+            const bool ok = p.site >= 0 && S.site_off[p.site + 1] - S.site_off[p.site] <= MAX_SITE;
+            s_site = ok ? p.site : -1;
+            s_new = p.nw;
+        }
     }
     __syncthreads();
     const int site = s_site;
@@ -599,7 +631,8 @@ hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, bool mid, hipStrea
 }
 
 hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s) {
-    hipLaunchKernelGGL(k_md_last, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
+    const int waves = (c->n_tiles + TILES_PER_WAVE - 1) / TILES_PER_WAVE;
+    hipLaunchKernelGGL(k_md_last, dim3((waves + 3) / 4), dim3(256), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.grid.H_scale,
                        a.st.target_idx, a.pr.mass, a.pr.x0, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx,
                        kick, c->err);

@@ -42,9 +42,13 @@ using namespace gbr;
 // Salt screening and pair cutoffs as the pair kernels use them (the EXT
 // variants; with kappa = 0 and no cutoffs the plain variants run):
 // kl2e = kappa log2(e), a = eps_in / eps_out, ak = a kappa, cut2 = cut^2 and
-// rgb2 = rgbmax^2 (FLT_MAX when off).
+// rgb2 = rgbmax^2 (FLT_MAX when off).  With both cutoffs the list holds packed
+// items, whose J atoms are listed in pk_j (64 per packed tile, replica-local
+// indices) with pk_hdr[P] = A << 7 | nj.
 struct PairExt {
     float kl2e, a, ak, cut2, rgb2;
+    const int32_t* pk_hdr;
+    const int32_t* pk_j;
 };
 
 namespace {
@@ -76,22 +80,41 @@ struct ItemGeom {
     int u_lim;      // i sub-blocks with a valid pair
     bool tri;       // triangle item (NI = 1 only)
     bool diag;      // diagonal item of a two-tile block (NI = 2 only)
+    bool packed;    // packed item: J atoms listed in jx (PK variants only)
     int phase;      // diagonal item: 0 = both tiles' own pairs, 1 = the cross pairs
     int k0, k1;     // rotation steps k0 .. k1 - 1 of the item
+    const int32_t* jx;
 };
 
-template <int NI>
-__device__ __forceinline__ ItemGeom item_geom(const int2 wi, const int32_t* __restrict__ atom_off) {
+// PK: the list may hold packed items (the EXT variants).  A packed item's I
+// block is always whole (atoms exist after it) and its J atoms all follow the
+// block, so its only invalid pairs are the empty J slots m >= nj.
+template <int NI, bool PK>
+__device__ __forceinline__ ItemGeom item_geom(const int2 wi, const int32_t* __restrict__ atom_off,
+                                              const PairExt& ext) {
     ItemGeom g;
     g.rep = wi.x & 0x3FFFFFF;
     const int type = (int)((unsigned)wi.x >> 30);
     const int half = (wi.x >> 26) & 3;              // block items: 0 whole, 1 / 2 halves
-    const int A = wi.y >> 16, B = wi.y & 0xFFFF;
+    const int A = (int)((unsigned)wi.y >> 16), B = wi.y & 0xFFFF;
     g.a0 = atom_off[g.rep];
     g.n = atom_off[g.rep + 1] - g.a0;
     g.tri = NI == 1 && type == ITEM_TRIANGLE;
     g.diag = NI == 2 && type == ITEM_DIAG;
-    if (NI == 2 && g.diag) {
+    g.packed = PK && type == ITEM_PACKED;
+    g.jx = nullptr;
+    if (PK && g.packed) {
+        const int P = wi.y;
+        const int h = ext.pk_hdr[P];
+        g.phase = 0;
+        g.ibase = (h >> 7) * 64 * NI;
+        g.jbase = 0;
+        g.nj = h & 127;
+        g.jx = ext.pk_j + (int64_t)P * 64;
+        g.u_lim = NI;
+        g.k0 = 0;
+        g.k1 = 64;
+    } else if (NI == 2 && g.diag) {
         g.phase = B;
         g.ibase = A * 128;                              // tile a; tile b follows it
         g.jbase = g.phase ? g.ibase + 64 : g.ibase;     // tile of LDS slot 0
@@ -123,18 +146,34 @@ __device__ __forceinline__ int item_li(const ItemGeom& g, int u, int lane) {
 // Validity of the pair of sub-block u in the masked loop (step k, j tile slot
 // m): j inside the replica and, in a block item on the diagonal, i < j; in a
 // triangle both atoms inside the replica and only lanes 0..31 on step 31.
-template <int NI>
+template <int NI, bool PK>
 __device__ __forceinline__ bool pair_ok(const ItemGeom& g, int lane, int k, int m, int li) {
     const bool jok = m < g.nj;
+    if (PK && g.packed) return jok;
     if (NI == 1 && g.tri) return jok & (lane < g.nj) & ((k < 31) | (lane < 32));
     return jok & (li < g.jbase + m);
+}
+
+// Replica-local index of J slot m (g.n for an empty slot).
+template <bool PK>
+__device__ __forceinline__ int j_of_slot(const ItemGeom& g, int m) {
+    if (PK && g.packed) return m < g.nj ? g.jx[m] : g.n;
+    return g.jbase + m;
+}
+
+// Replica-local atom loaded into J slot `lane` of a tile starting at tb (a
+// packed item's listed atom; past the end the last valid one).
+template <bool PK>
+__device__ __forceinline__ int j_fill(const ItemGeom& g, int tb, int lane) {
+    if (PK && g.packed) return g.jx[min(lane, g.nj - 1)];
+    return min(tb + lane, g.n - 1);
 }
 
 // Runs the item's steps through kloop(full, k0, k1): unmasked where every pair
 // is valid (a block item entirely before a full j tile; steps 0..30 of a
 // triangle on a full tile), masked for the rest.  Each variant is called from
 // one place so that it is inlined.
-template <int NI, typename K>
+template <int NI, bool PK, typename K>
 __device__ __forceinline__ void run_item(const ItemGeom& g, K& kloop) {
     if constexpr (NI == 1) {
         int f1 = g.k0;
@@ -142,7 +181,8 @@ __device__ __forceinline__ void run_item(const ItemGeom& g, K& kloop) {
         if (f1 > g.k0) kloop(std::true_type{}, g.k0, f1);
         if (f1 < g.k1) kloop(std::false_type{}, f1, g.k1);
     } else {
-        if (g.nj == 64 && g.ibase + 64 * NI <= g.jbase) kloop(std::true_type{}, g.k0, g.k1);
+        const bool full = (PK && g.packed) ? g.nj == 64 : (g.nj == 64 && g.ibase + 64 * NI <= g.jbase);
+        if (full) kloop(std::true_type{}, g.k0, g.k1);
         else kloop(std::false_type{}, g.k0, g.k1);
     }
 }
@@ -197,7 +237,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
     const float ixmax = 1.0f / HCT_FAR_XMAX;
     if (n_dev) n_items = n_dev[0];                // a culled list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
-        const ItemGeom g = item_geom<NI>(items[it], atom_off);
+        const ItemGeom g = item_geom<NI, EXT>(items[it], atom_off, ext);
         float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], s2i[NI], s3i[NI], mi[NI], sxi[NI], acc[NI];
         int li[NI];
 #pragma unroll
@@ -214,7 +254,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
             acc[u] = 0.0f;
         }
         auto fill = [&](int slot, int tb) {
-            const int ja = g.a0 + min(tb + lane, g.n - 1);
+            const int ja = g.a0 + j_fill<EXT>(g, tb, lane);
             const float rt = rho[ja] - offset, s = screen[ja] * rt;
             lds[wv][slot][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], s);
             lds[wv][slot][1][lane] = make_float4(rt, fmaxf(rt, s), s * ixmax, s * s * s);
@@ -255,7 +295,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
 #pragma unroll
                 for (int u = 0; u < NI; ++u) {
                     if (FULL || u < g.u_lim) {
-                        const float h = pair(u, p0, p1, FULL || pair_ok<NI>(g, lane, k, m, li[u]), full);
+                        const float h = pair(u, p0, p1, FULL || pair_ok<NI, EXT>(g, lane, k, m, li[u]), full);
                         cj = (u == 0) ? h : cj + h;
                     }
                 }
@@ -273,17 +313,17 @@ __global__ __launch_bounds__(256) void k_born_pair(
                                                                     ok1, std::false_type{}));
                 });
             } else {
-                run_item<NI>(g, kloop);
+                run_item<NI, EXT>(g, kloop);
             }
         } else {
-            run_item<NI>(g, kloop);
+            run_item<NI, EXT>(g, kloop);
         }
         wave_lds_fence();
 #pragma unroll
         for (int u = 0; u < NI; ++u)
             if (u < g.u_lim && li[u] < g.n)
                 atomic_add_fx(&psi_fx[g.a0 + li[u]], to_fixed_f(acc[u], FXF_FORCE, err));
-        const int jl = g.jbase + ((lane + g.k1) & 63);
+        const int jl = j_of_slot<EXT>(g, (lane + g.k1) & 63);
         if (jl < g.n) atomic_add_fx(&psi_fx[g.a0 + jl], to_fixed_f(accj[0], FXF_FORCE, err));
         if (NSL > 1 && g.diag && g.u_lim > 1) {
             const int jl1 = g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63);
@@ -325,8 +365,21 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     const float hl = 0.5f / LOG2E;               // D = D2 / log2(e)
     const float wq = -0.25f * taup;
     if (n_dev) n_items = n_dev[0];                // a culled list: its device count
+    // energy sums of the wavefront's current replica (valid in lane 63); one
+    // set of atomics per replica change rather than per item, so that the
+    // items of one large replica do not all meet at its three energy slots
+    int e_rep = -1;
+    long long e_sum[3] = {0, 0, 0};
+    auto flush_e = [&]() {
+        if (e_rep >= 0 && lane == 63) {
+            atomic_add_fx(&energy_fx[4 * e_rep + 0], e_sum[0]);
+            atomic_add_fx(&energy_fx[4 * e_rep + 1], e_sum[1]);
+            atomic_add_fx(&energy_fx[4 * e_rep + 2], e_sum[2]);
+        }
+        e_sum[0] = e_sum[1] = e_sum[2] = 0;
+    };
     for (int it = logical_wave(); it < n_items; it += stride) {
-        const ItemGeom g = item_geom<NI>(items[it], atom_off);
+        const ItemGeom g = item_geom<NI, EXT>(items[it], atom_off, ext);
         float xi[NI], yi[NI], zi[NI], qi[NI], Ri[NI], Li[NI], hsi[NI], sei[NI];
         float fxi[NI], fyi[NI], fzi[NI], dRi[NI], dqi[NI];
         int li[NI];
@@ -343,7 +396,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             fxi[u] = fyi[u] = fzi[u] = dRi[u] = dqi[u] = 0.0f;
         }
         auto fill = [&](int slot, int tb) {
-            const int ja = g.a0 + min(tb + lane, g.n - 1);
+            const int ja = g.a0 + j_fill<EXT>(g, tb, lane);
             const float Rj = Rb[ja];
             lds[wv][slot][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], q[ja] * sq_ke_in);
             lds[wv][slot][1][lane] = make_float4(Rj, lc / Rj, 0.5f * sigma[ja], 2.0f * sqrtf(eps[ja]));
@@ -431,7 +484,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
 #pragma unroll
                 for (int u = 0; u < NI; ++u)
                     if (FULL || u < g.u_lim)
-                        pair(u, p0, p1, FULL || pair_ok<NI>(g, lane, k, m, li[u]), full, c, u == 0);
+                        pair(u, p0, p1, FULL || pair_ok<NI, EXT>(g, lane, k, m, li[u]), full, c, u == 0);
                 rotate(accj[0], c);
             }
         };
@@ -448,10 +501,10 @@ __global__ __launch_bounds__(256) void k_energy_pair(
                     }
                 });
             } else {
-                run_item<NI>(g, kloop);
+                run_item<NI, EXT>(g, kloop);
             }
         } else {
-            run_item<NI>(g, kloop);
+            run_item<NI, EXT>(g, kloop);
         }
         wave_lds_fence();
 #pragma unroll
@@ -474,19 +527,23 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             atomic_add_fx(&dEdR_fx[a], to_fixed_f(EXT ? aj.R : aj.R * taup, FXF_FORCE, err));
             if (GQ) atomic_add_fx(&dEdq_fx[a], to_fixed_f(aj.q * sq_ke_in, FXF_FORCE, err));
         };
-        flush_j(g.jbase + ((lane + g.k1) & 63), accj[0]);
+        flush_j(j_of_slot<EXT>(g, (lane + g.k1) & 63), accj[0]);
         if (NSL > 1 && g.diag && g.u_lim > 1)
             flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
         // per-lane energies to fixed point, summed over the wavefront as integers
+        // and kept (lane 63) while the wavefront's items stay in one replica
         const long long sgb = wave_sum_i64_lane63(to_fixed_f(EXT ? -e_g : -taup * e_g, FXF_ENERGY, err));
         const long long sc = wave_sum_i64_lane63(to_fixed_f(e_c, FXF_ENERGY, err));
         const long long slj = wave_sum_i64_lane63(to_fixed_f(e_lj, FXF_ENERGY, err));
-        if (lane == 63) {
-            atomic_add_fx(&energy_fx[4 * g.rep + 0], sgb);
-            atomic_add_fx(&energy_fx[4 * g.rep + 1], sc);
-            atomic_add_fx(&energy_fx[4 * g.rep + 2], slj);
+        if (g.rep != e_rep) {
+            flush_e();
+            e_rep = g.rep;
         }
+        e_sum[0] += sgb;
+        e_sum[1] += sc;
+        e_sum[2] += slj;
     }
+    flush_e();
 }
 
 // ------------------------------------------------- chain rule through psi
@@ -515,7 +572,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     const float ixmax = 1.0f / HCT_FAR_XMAX;
     if (n_dev) n_items = n_dev[0];                // a culled list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
-        const ItemGeom g = item_geom<NI>(items[it], atom_off);
+        const ItemGeom g = item_geom<NI, EXT>(items[it], atom_off, ext);
         float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], ci[NI], Si[NI], mi[NI], sxi[NI], s2i[NI], s3i[NI];
         float fxi[NI], fyi[NI], fzi[NI], dri[NI];
         int li[NI];
@@ -535,7 +592,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
             fxi[u] = fyi[u] = fzi[u] = dri[u] = 0.0f;
         }
         auto fill = [&](int slot, int tb) {
-            const int ja = g.a0 + min(tb + lane, g.n - 1);
+            const int ja = g.a0 + j_fill<EXT>(g, tb, lane);
             const float rt = rho[ja] - offset, S = screen[ja], s = S * rt;
             lds[wv][slot][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], cc[ja]);
             lds[wv][slot][1][lane] = make_float4(rt, s, fmaxf(rt, s), s * ixmax);
@@ -602,7 +659,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
 #pragma unroll
                 for (int u = 0; u < NI; ++u)
                     if (FULL || u < g.u_lim)
-                        pair(u, p0, p1, p2, FULL || pair_ok<NI>(g, lane, k, m, li[u]), full, c, u == 0);
+                        pair(u, p0, p1, p2, FULL || pair_ok<NI, EXT>(g, lane, k, m, li[u]), full, c, u == 0);
                 rotate(accj[0], c);
             }
         };
@@ -620,10 +677,10 @@ __global__ __launch_bounds__(256) void k_chain_pair(
                     }
                 });
             } else {
-                run_item<NI>(g, kloop);
+                run_item<NI, EXT>(g, kloop);
             }
         } else {
-            run_item<NI>(g, kloop);
+            run_item<NI, EXT>(g, kloop);
         }
         wave_lds_fence();
 #pragma unroll
@@ -644,20 +701,30 @@ __global__ __launch_bounds__(256) void k_chain_pair(
             atomic_add_fx(&force_fx[2 * ntot + a], to_fixed_f(aj.z, FXF_FORCE, err));
             if (RHO) atomic_add_fx(&dEdrho_fx[a], to_fixed_f(aj.r, FXF_FORCE, err));
         };
-        flush_j(g.jbase + ((lane + g.k1) & 63), accj[0]);
+        flush_j(j_of_slot<EXT>(g, (lane + g.k1) & 63), accj[0]);
         if (NSL > 1 && g.diag && g.u_lim > 1)
             flush_j(g.ibase + 64 + ((lane + (g.phase ? 64 : 32)) & 63), accj[NSL - 1]);
     }
 }
 
-// ------------------------------------------------------------- culling
+// ------------------------------------------------------------- packing
+// With both cutoffs the pair passes run, per list and radius, the list's
+// intra-block items (a fixed prefix) followed by packed items built at every
+// evaluation from the current positions.
+
 // Per-tile bounding boxes: one wavefront per tile, min / max over its atoms.
-// Also clears the four survivor counters (the culling kernels run after).
+// Also resets the eight list counters to their intra-block item counts (the
+// packing kernels run after).
+struct CountInit {
+    int32_t v[8];
+};
+
 __global__ __launch_bounds__(256) void k_tile_boxes(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off, int ntot,
-    const float* __restrict__ xyz, float4* __restrict__ box, int32_t* __restrict__ counts)
+    const float* __restrict__ xyz, float4* __restrict__ box, int32_t* __restrict__ counts,
+    CountInit init)
 {
-    if (blockIdx.x == 0 && threadIdx.x < 8) counts[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 8) counts[threadIdx.x] = init.v[threadIdx.x];
     const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     if (t >= n_tiles) return;
     const int lane = threadIdx.x & 63;
@@ -681,73 +748,144 @@ __global__ __launch_bounds__(256) void k_tile_boxes(
     }
 }
 
-// Culling of a list: block items whose I block (NI tiles) and J tile boxes
-// are farther apart than rc are dropped, the rest (and every triangle or
-// diagonal item) appended to the culled list.  A workgroup takes CULL_ROUNDS
-// rounds of 256 consecutive items, keeps their survivors in list order and
-// reserves its output range with one atomic; the workgroups' ranges land in
-// arbitrary order, which the fixed-point sums do not depend on.
-constexpr int CULL_ROUNDS = 8;
-
-__device__ __forceinline__ bool cull_keep(int2 wi, int ni, const int32_t* __restrict__ atom_off,
-                                          const int32_t* __restrict__ tile_base,
-                                          const float4* __restrict__ box, float rc2) {
-    if (((unsigned)wi.x >> 30) != (unsigned)ITEM_BLOCK) return true;
-    const int rep = wi.x & 0x3FFFFFF;
-    const int A = wi.y >> 16, B = wi.y & 0xFFFF;
-    const int T = (atom_off[rep + 1] - atom_off[rep] + 63) >> 6;
-    const int tb = tile_base[rep];
-    float4 ilo = box[2 * (tb + A * ni)], ihi = box[2 * (tb + A * ni) + 1];
-    for (int u = 1; u < ni && A * ni + u < T; ++u) {
-        const float4 l = box[2 * (tb + A * ni + u)], h = box[2 * (tb + A * ni + u) + 1];
-        ilo = make_float4(fminf(ilo.x, l.x), fminf(ilo.y, l.y), fminf(ilo.z, l.z), 0.0f);
-        ihi = make_float4(fmaxf(ihi.x, h.x), fmaxf(ihi.y, h.y), fmaxf(ihi.z, h.z), 0.0f);
-    }
-    const float4 jlo = box[2 * (tb + B)], jhi = box[2 * (tb + B) + 1];
-    const float dx = fmaxf(0.0f, fmaxf(ilo.x - jhi.x, jlo.x - ihi.x));
-    const float dy = fmaxf(0.0f, fmaxf(ilo.y - jhi.y, jlo.y - ihi.y));
-    const float dz = fmaxf(0.0f, fmaxf(ilo.z - jhi.z, jlo.z - ihi.z));
-    return dx * dx + dy * dy + dz * dz < rc2;
+// Packing, in two passes.  Every I block (rep, A) with tiles after it owns
+// the packed tiles P0 .. P0 + (T - t1) - 1 (t1: the first tile after the
+// block), as many as it has tiles after it, and their 64 J slots each.
+//  k_pack_atoms: one wavefront per window of up to 64 tiles after a block;
+//    the tiles whose box comes within rc of the block's box, then their atoms
+//    within rc of it, appended to the block's slots (one atomic per window on
+//    the block's atom count; the windows' atoms land in arbitrary order).
+//  k_pack_items: one lane per block; its atoms form ceil(count / 64) packed
+//    items {rep | ITEM_PACKED << 30, P}, pk_hdr[P] = A << 7 | nj, appended to
+//    the list after its intra-block items; the count is cleared for the next
+//    evaluation.
+// Every pair the packing drops is farther apart than rc, so the kernels'
+// cutoff would have made its terms exact zeros; the order of the J atoms and
+// of the items changes no result (fixed-point sums).
+__device__ __forceinline__ float box_gap2(float4 alo, float4 ahi, float4 blo, float4 bhi) {
+    const float dx = fmaxf(0.0f, fmaxf(alo.x - bhi.x, blo.x - ahi.x));
+    const float dy = fmaxf(0.0f, fmaxf(alo.y - bhi.y, blo.y - ahi.y));
+    const float dz = fmaxf(0.0f, fmaxf(alo.z - bhi.z, blo.z - ahi.z));
+    return dx * dx + dy * dy + dz * dz;
 }
 
-__global__ __launch_bounds__(256) void k_cull(
-    const int2* __restrict__ items, int n_items, int ni, const int32_t* __restrict__ atom_off,
-    const int32_t* __restrict__ tile_base, const float4* __restrict__ box, float rc2,
-    int2* __restrict__ out, int32_t* __restrict__ count)
+constexpr int PACK_BATCH = 4;       // tiles whose atoms are loaded together
+
+__global__ __launch_bounds__(256) void k_pack_atoms(
+    const int4* __restrict__ win, int n_win, int ni,
+    const int32_t* __restrict__ atom_off, const int32_t* __restrict__ tile_base,
+    const float4* __restrict__ box, const float* __restrict__ xyz, int ntot, float rc2,
+    int32_t* __restrict__ blk_count, int32_t* __restrict__ pk_j)
 {
-    __shared__ int s_cnt[CULL_ROUNDS * 4];
-    __shared__ int s_base;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const long long first = (long long)blockIdx.x * (256 * CULL_ROUNDS);
-    int2 wi[CULL_ROUNDS];
-    unsigned long long m[CULL_ROUNDS];
+    __shared__ unsigned long long s_mask[MAXW][64];
+    __shared__ int s_tile[MAXW][64];
+    const int lane = threadIdx.x & 63, wv = wave_in_group();
+    const int wi = blockIdx.x * (blockDim.x >> 6) + wv;
+    if (wi >= n_win) return;
+    // {block, A << 16 | first tile, the block's first packed tile, replica}
+    const int4 wd = win[wi];
+    const int rep = wd.w, A = (int)((unsigned)wd.y >> 16), c0 = wd.y & 0xFFFF;
+    const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
+    const int T = (n + 63) >> 6, tb = tile_base[rep];
+    const int t0 = A * ni, t1 = min(T, t0 + ni);
+    float4 lo = box[2 * (tb + t0)], hi = box[2 * (tb + t0) + 1];
+    for (int t = t0 + 1; t < t1; ++t) {
+        const float4 l = box[2 * (tb + t)], h = box[2 * (tb + t) + 1];
+        lo = make_float4(fminf(lo.x, l.x), fminf(lo.y, l.y), fminf(lo.z, l.z), 0.0f);
+        hi = make_float4(fmaxf(hi.x, h.x), fmaxf(hi.y, h.y), fmaxf(hi.z, h.z), 0.0f);
+    }
+    const int t = c0 + lane;
+    bool near = false;
+    if (t < T) near = box_gap2(lo, hi, box[2 * (tb + t)], box[2 * (tb + t) + 1]) < rc2;
+    unsigned long long nm = __ballot(near);
+    if (!nm) return;
+    int nn = 0, total = 0;
+    while (nm) {
+        int bt[PACK_BATCH];
+        float x[PACK_BATCH], y[PACK_BATCH], z[PACK_BATCH];
 #pragma unroll
-    for (int r = 0; r < CULL_ROUNDS; ++r) {
-        const long long i = first + r * 256 + threadIdx.x;
-        bool keep = false;
-        wi[r] = make_int2(0, 0);
-        if (i < n_items) {
-            wi[r] = items[i];
-            keep = cull_keep(wi[r], ni, atom_off, tile_base, box, rc2);
+        for (int k = 0; k < PACK_BATCH; ++k) {
+            bt[k] = -1;
+            if (nm) {
+                bt[k] = c0 + __ffsll((long long)nm) - 1;
+                nm &= nm - 1ull;
+                const int jl = min(bt[k] * 64 + lane, n - 1);
+                x[k] = xyz[a0 + jl]; y[k] = xyz[ntot + a0 + jl]; z[k] = xyz[2 * ntot + a0 + jl];
+            }
         }
-        m[r] = __ballot(keep);
-        if (lane == 0) s_cnt[r * 4 + w] = __popcll(m[r]);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int total = 0;
-        for (int k = 0; k < CULL_ROUNDS * 4; ++k) {   // exclusive prefix in list order
-            const int c = s_cnt[k];
-            s_cnt[k] = total;
-            total += c;
+#pragma unroll
+        for (int k = 0; k < PACK_BATCH; ++k) {
+            if (bt[k] < 0) break;
+            const float dx = fmaxf(0.0f, fmaxf(lo.x - x[k], x[k] - hi.x));
+            const float dy = fmaxf(0.0f, fmaxf(lo.y - y[k], y[k] - hi.y));
+            const float dz = fmaxf(0.0f, fmaxf(lo.z - z[k], z[k] - hi.z));
+            const bool keep = bt[k] * 64 + lane < n && dx * dx + dy * dy + dz * dz < rc2;
+            const unsigned long long am = __ballot(keep);
+            if (am) {
+                if (lane == 0) {
+                    s_mask[wv][nn] = am;
+                    s_tile[wv][nn] = bt[k];
+                }
+                ++nn;
+                total += __popcll(am);
+            }
         }
-        s_base = total ? atomicAdd(count, total) : 0;
     }
-    __syncthreads();
+    if (total == 0) return;
+    int off = 0;
+    if (lane == 0) off = atomicAdd(&blk_count[wd.x], total);
+    off = __shfl(off, 0, 64);
+    wave_lds_fence();
     const unsigned long long below = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int r = 0; r < CULL_ROUNDS; ++r)
-        if ((m[r] >> lane) & 1ull) out[s_base + s_cnt[r * 4 + w] + __popcll(m[r] & below)] = wi[r];
+    int32_t* dst = pk_j + (int64_t)wd.z * 64 + off;
+    for (int k = 0; k < nn; ++k) {
+        const unsigned long long am = s_mask[wv][k];
+        if ((am >> lane) & 1ull) dst[__popcll(am & below)] = s_tile[wv][k] * 64 + lane;
+        dst += __popcll(am);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_pack_items(
+    const int2* __restrict__ iblk, const int32_t* __restrict__ blk_p0, int n_iblk,
+    int32_t* __restrict__ blk_count, int2* __restrict__ items, int32_t* __restrict__ count,
+    int32_t* __restrict__ pk_hdr)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+    if (w < n_iblk) {
+        cnt = blk_count[w];
+        blk_count[w] = 0;
+    }
+    const int nt = (cnt + 63) >> 6;
+    int pre = nt;                                  // inclusive prefix over the wavefront
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(pre, o, 64);
+        if (lane >= o) pre += v;
+    }
+    const int total = __shfl(pre, 63, 64);
+    if (total == 0) return;
+    int base = 0;
+    if (lane == 63) base = atomicAdd(count, total);
+    base = __shfl(base, 63, 64);
+    int2 ib = make_int2(0, 0);
+    int p0 = 0;
+    if (nt > 0) {
+        ib = iblk[w];
+        p0 = blk_p0[w];
+    }
+    // the wavefront writes block L's items together, block by block
+    for (int L = 0; L < 64; ++L) {
+        const int ntL = __shfl(nt, L, 64);
+        if (ntL == 0) continue;
+        const int slot0 = base + __shfl(pre, L, 64) - ntL;
+        const int cntL = __shfl(cnt, L, 64), repL = __shfl(ib.x, L, 64), AL = __shfl(ib.y, L, 64);
+        const int p0L = __shfl(p0, L, 64);
+        for (int p = lane; p < ntL; p += 64) {
+            items[slot0 + p] = make_int2(repL | (ITEM_PACKED << 30), p0L + p);
+            pk_hdr[p0L + p] = (AL << 7) | min(64, cntL - 64 * p);
+        }
+    }
 }
 
 int grid_for(const gbr_ctx* c, int n_items) {
@@ -779,13 +917,17 @@ const PairList& list_for(const gbr_ctx* c, int ni) {
 
 namespace gbr {
 
-static PairExt make_pair_ext(const gbr_gb_params& p) {
+// kind: the packed lists of radius rgbmax (0, descreening passes) or cut (1).
+static PairExt make_pair_ext(const gbr_ctx* c, const PairList& L, int kind) {
+    const gbr_gb_params& p = c->prm;
     PairExt e;
     e.kl2e = (float)(p.kappa * 1.4426950408889634);
     e.a = (float)(p.eps_in / p.eps_out);
     e.ak = (float)(p.eps_in / p.eps_out * p.kappa);
     e.cut2 = p.cut > 0 ? (float)(p.cut * p.cut) : FLT_MAX;
     e.rgb2 = p.rgbmax > 0 ? (float)(p.rgbmax * p.rgbmax) : FLT_MAX;
+    e.pk_hdr = c->cull ? L.pk_hdr[kind] : nullptr;
+    e.pk_j = c->cull ? L.pk_j[kind] : nullptr;
     return e;
 }
 
@@ -795,8 +937,11 @@ static bool uses_ext(const gbr_ctx* c) {
 
 hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s) {
     if (!c->cull) return hipSuccess;
+    CountInit init;
+    for (int k = 0; k < 4; ++k)
+        for (int v = 0; v < 2; ++v) init.v[2 * k + v] = c->lists[k].n_intra;
     hipLaunchKernelGGL(k_tile_boxes, dim3((c->n_tiles + 3) / 4), dim3(256), 0, s, c->tiles, c->n_tiles,
-                       c->atom_off, c->n_atoms, xyz, c->tile_box, c->cull_count);
+                       c->atom_off, c->n_atoms, xyz, c->tile_box, c->cull_count, init);
     // the tile boxes' FP32 bounds are exact (min / max of the stored
     // coordinates); the margin covers the rounding of the kernels' own r^2
     const double rc[2] = {c->prm.rgbmax * (1.0 + 1e-5) + 1e-4, c->prm.cut * (1.0 + 1e-5) + 1e-4};
@@ -808,11 +953,13 @@ hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s) {
         if (done[idx][kind[k]]) continue;
         done[idx][kind[k]] = true;
         const PairList& L = c->lists[idx];
-        if (L.n_items == 0) continue;
-        const int per_group = 256 * CULL_ROUNDS;
-        hipLaunchKernelGGL(k_cull, dim3((L.n_items + per_group - 1) / per_group), dim3(256), 0, s, L.items, L.n_items, L.ni,
-                           c->atom_off, c->tile_base, c->tile_box, (float)(rc[kind[k]] * rc[kind[k]]),
-                           L.culled[kind[k]], L.n_culled[kind[k]]);
+        if (L.n_iblk == 0) continue;
+        const int v = kind[k];
+        hipLaunchKernelGGL(k_pack_atoms, dim3((L.n_win + 3) / 4), dim3(256), 0, s, L.win, L.n_win,
+                           L.ni, c->atom_off, c->tile_base, c->tile_box, xyz, c->n_atoms,
+                           (float)(rc[v] * rc[v]), L.blk_count[v], L.pk_j[v]);
+        hipLaunchKernelGGL(k_pack_items, dim3((L.n_iblk + 63) / 64), dim3(64), 0, s, L.iblk, L.blk_p0,
+                           L.n_iblk, L.blk_count[v], L.culled[v], L.n_culled[v], L.pk_hdr[v]);
     }
     return hipGetLastError();
 }
@@ -826,7 +973,7 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
     const int2* items = c->cull ? L.culled[0] : L.items;
     const int32_t* n_dev = c->cull ? L.n_culled[0] : nullptr;
     const float off = (float)c->prm.offset;
-    const PairExt pe = make_pair_ext(c->prm);
+    const PairExt pe = make_pair_ext(c, L, 0);
     const bool ext = uses_ext(c);
 #define GBR_BORN(NI, EX) hipExtLaunchKernelGGL((k_born_pair<NI, EX>), grid, block, 0, s, ev.start, ev.stop, 0, \
         items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, off, pe, c->psi_fx, c->err)
@@ -852,7 +999,7 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     const int32_t* n_dev = c->cull ? L.n_culled[1] : nullptr;
     const float sq = (float)sqrt(c->prm.k_e / c->prm.eps_in);
     const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
-    const PairExt pe = make_pair_ext(c->prm);
+    const PairExt pe = make_pair_ext(c, L, 1);
 #define GBR_EN(NI, GQ, EX) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ, EX>), grid, block, 0, s, ev.start, \
         ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, pe, \
         force_fx, c->dEdR_fx, energy_fx, dEdq_fx, c->err)
@@ -879,7 +1026,7 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
     const int2* items = c->cull ? L.culled[0] : L.items;
     const int32_t* n_dev = c->cull ? L.n_culled[0] : nullptr;
     const float off = (float)c->prm.offset;
-    const PairExt pe = make_pair_ext(c->prm);
+    const PairExt pe = make_pair_ext(c, L, 0);
 #define GBR_CH(NI, RH, EX) hipExtLaunchKernelGGL((k_chain_pair<NI, RH, EX>), grid, block, 0, s, ev.start, \
         ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, c->chain_c, off, pe, \
         force_fx, dEdrho_fx, c->err)

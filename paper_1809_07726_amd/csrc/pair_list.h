@@ -38,7 +38,7 @@
 
 namespace gbr {
 
-enum : int32_t { ITEM_BLOCK = 0, ITEM_DIAG = 1, ITEM_TRIANGLE = 2 };
+enum : int32_t { ITEM_BLOCK = 0, ITEM_DIAG = 1, ITEM_TRIANGLE = 2, ITEM_PACKED = 3 };
 
 constexpr int32_t MAX_TILES = 65535;          // per replica (16-bit tile fields)
 constexpr int32_t MAX_REPLICAS = 1 << 26;     // 26-bit replica field
@@ -122,6 +122,47 @@ inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vec
         tmp.clear();
         for (size_t i : idx) tmp.push_back(out[i]);
         std::copy(tmp.begin(), tmp.end(), out.begin() + (ptrdiff_t)b);
+    }
+}
+
+// Runs with pair cutoffs replace the block items whose J tile lies after
+// their I block by ITEM_PACKED items (x = rep | ITEM_PACKED << 30, y = P):
+// the atoms after the block that come within the cutoff of the block, packed
+// 64 at a time on the device at every evaluation.  The fixed part: the items
+// whose pairs lie inside one I block (in list order); the I blocks {rep, A}
+// with tiles after them, each owning as many packed tiles (from p0 on) as it
+// has tiles after it (cap in all); and the windows of up to 64 of those tiles
+// that the packing scans, {block, A << 16 | first tile, block's p0, replica}.
+struct PackWindow {
+    int32_t blk, a_c0, p0, rep;
+};
+
+inline void build_packed_parts(const int32_t* off, int32_t n_rep, int ni,
+                               const std::vector<PairItem>& items, std::vector<PairItem>& intra,
+                               std::vector<PairItem>& iblocks, std::vector<int32_t>& p0,
+                               std::vector<PackWindow>& windows, int64_t& cap) {
+    intra.clear();
+    iblocks.clear();
+    p0.clear();
+    windows.clear();
+    cap = 0;
+    for (const PairItem& it : items) {
+        const bool block = ((uint32_t)it.x >> 30) == (uint32_t)ITEM_BLOCK;
+        const int32_t A = (int32_t)((uint32_t)it.y >> 16), B = it.y & 0xFFFF;
+        if (!block || B < (A + 1) * ni) intra.push_back(it);
+    }
+    for (int32_t r = 0; r < n_rep; ++r) {
+        const int32_t T = (off[r + 1] - off[r] + 63) / 64;
+        for (int32_t a = 0; a * ni < T; ++a) {
+            const int32_t t1 = std::min(T, (a + 1) * ni);
+            if (t1 >= T) continue;
+            const int32_t blk = (int32_t)iblocks.size();
+            iblocks.push_back(PairItem{r, a});
+            p0.push_back((int32_t)cap);
+            for (int32_t c0 = t1; c0 < T; c0 += 64)
+                windows.push_back(PackWindow{blk, (a << 16) | c0, (int32_t)cap, r});
+            cap += T - t1;
+        }
     }
 }
 

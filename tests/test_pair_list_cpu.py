@@ -192,3 +192,85 @@ def test_rotating_accumulator_lands_on_lane_plus_k(K, o):
         np.add.at(contrib, j, c)
         acc = np.roll(acc, -1) + c
     assert np.allclose(acc, contrib[(lane + K + o) & 63], rtol=0, atol=1e-12)
+
+
+PACK_HARNESS = r"""
+#include <cstdio>
+#include <cstdlib>
+#include "pair_list.h"
+int main(int argc, char** argv) {
+    const int ni = std::atoi(argv[1]);
+    std::vector<int32_t> off{0};
+    for (int k = 2; k < argc; ++k) off.push_back(off.back() + std::atoi(argv[k]));
+    std::vector<gbr::PairItem> items, intra, blocks;
+    std::vector<int32_t> p0;
+    std::vector<gbr::PackWindow> wins;
+    int64_t cap = 0;
+    gbr::build_pair_items(off.data(), (int32_t)off.size() - 1, ni, items);
+    gbr::build_packed_parts(off.data(), (int32_t)off.size() - 1, ni, items, intra, blocks, p0, wins, cap);
+    std::printf("cap %lld\n", (long long)cap);
+    for (const auto& it : intra)
+        std::printf("I %d %d %d %d %d\n", it.x & 0x3FFFFFF, (int)((unsigned)it.x >> 30), it.y >> 16,
+                    it.y & 0xFFFF, (it.x >> 26) & 3);
+    for (size_t b = 0; b < blocks.size(); ++b)
+        std::printf("B %d %d %d\n", blocks[b].x, blocks[b].y, p0[b]);
+    for (const auto& w : wins) std::printf("W %d %d %d %d %d\n", w.blk, w.a_c0 & 0xFFFF, w.p0, w.a_c0 >> 16, w.rep);
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def pack_harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("packparts")
+    src, exe = d / "p.cpp", d / "p"
+    src.write_text(PACK_HARNESS)
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)])
+    return str(exe)
+
+
+@pytest.mark.parametrize("ni", [1, 2, 4, 8])
+def test_packed_lists_cover_every_pair_once(harness, pack_harness, ni):
+    """With pair cutoffs the passes run the intra-block items plus, for every
+    I block with tiles after it, packed items holding (at most) every atom
+    after the block.  With a radius that keeps every atom, the intra-block
+    items and the block-times-later-atoms pairs meet every pair of every
+    replica exactly once; each block owns one packed tile per tile after it
+    (enough for all those atoms), its windows cover those tiles once in
+    pieces of at most 64, and the intra items keep the list's order."""
+    sizes = [1, 63, 64, 65, 200, 511, 640, 1000, 2100]
+    out = subprocess.check_output([pack_harness, str(ni)] + [str(s) for s in sizes], text=True).splitlines()
+    cap = int(out[0].split()[1])
+    intra = np.array([list(map(int, l.split()[1:])) for l in out if l[0] == "I"], np.int64).reshape(-1, 5)
+    blocks = np.array([list(map(int, l.split()[1:])) for l in out if l[0] == "B"], np.int64).reshape(-1, 3)
+    wins = np.array([list(map(int, l.split()[1:])) for l in out if l[0] == "W"], np.int64).reshape(-1, 5)
+    full = _items(harness, ni, sizes)
+    A_, B_ = full[:, 2], full[:, 3]
+    inside = (full[:, 1] != 0) | (B_ < (A_ + 1) * ni)
+    assert np.array_equal(intra, full[inside])
+    p_next = 0
+    for b, (r, A, p0) in enumerate(blocks):
+        n = sizes[r]
+        T = (n + 63) // 64
+        t1 = min(T, (A + 1) * ni)
+        assert t1 < T and p0 == p_next
+        p_next += T - t1
+        w = wins[wins[:, 0] == b]
+        tiles = np.concatenate([np.arange(c0, min(c0 + 64, T)) for c0 in w[:, 1]])
+        assert np.array_equal(tiles, np.arange(t1, T)) and np.all(w[:, 2] == p0)
+        assert np.all(w[:, 3] == A) and np.all(w[:, 4] == r)
+    assert cap == p_next
+    for r, n in enumerate(sizes):
+        its = intra[intra[:, 0] == r]
+        P = [_pairs_of_item(n, ni, *it[1:]) for it in its]
+        for (rr, A, p0) in blocks[blocks[:, 0] == r]:
+            T = (n + 63) // 64
+            t1 = min(T, (A + 1) * ni)
+            i = np.arange(64 * ni * A, 64 * t1)
+            j = np.arange(64 * t1, n)
+            P.append(np.stack(np.meshgrid(i, j, indexing="ij"), -1).reshape(-1, 2))
+        P = np.concatenate(P) if P else np.zeros((0, 2), int)
+        a, bb = np.minimum(P[:, 0], P[:, 1]), np.maximum(P[:, 0], P[:, 1])
+        assert np.all(a != bb) and P.max(initial=0) < n
+        key = a * n + bb
+        assert key.size == n * (n - 1) // 2 and np.unique(key).size == key.size, (n, ni)
