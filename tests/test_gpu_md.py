@@ -120,6 +120,60 @@ def test_graph_replay_is_bitwise_equal_to_eager():
         assert np.array_equal(eager[k], graph[k]), k
 
 
+def test_graph_replay_with_hamiltonian_exchanges_is_bitwise_equal_to_eager():
+    """Captured step graphs on a 2 T x 3 H grid (exchanges every 5 steps, so
+    the graphs hold the Hamiltonian swaps and the force rescaling after
+    them) give the same bits as eager launches."""
+    base = synth.draw_system(160, 4343, 2, 1)
+    reps = [synth.jitter_copy(base, 700 + r) for r in range(12)]
+    b = synth.assemble([base, base], 6, (-0.2,), (7.0,), (300.0, 330.0), (synth.DIM_H, synth.DIM_T),
+                       per_replica=reps, H_scale=(1.0, 0.9, 0.8), mc_every=5, ex_every=5)
+    b = with_oracle_gref(b)
+    eager = _gpu_md(b, 9, [12, 13])
+    graph = _gpu_md(b, 9, [12, 13], graph=True)
+    for e, g in zip(eager, graph):
+        for k in ("xyz", "v", "q", "site_state", "target_idx", "grid_rep", "F_fx"):
+            assert np.array_equal(e[k], g[k]), k
+    assert not np.array_equal(eager[-1]["target_idx"][:, synth.DIM_H], b["target_idx"][:, synth.DIM_H])
+
+
+def test_gpu_hamiltonian_exchange_samples_the_pair_boltzmann_weights():
+    """32 frozen two-replica systems on a 2-level Hamiltonian grid (scales 1.0
+    and 0.8), exchange attempts every step on the GPU: each pair holds the
+    arrangement (replica 0 at level 0) with probability w_A / (w_A + w_B) of
+    the Boltzmann weights of the two arrangements, from the oracle's
+    energies."""
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch
+    lams = (1.0, 0.8)
+    base = synth.draw_system(16, 51, 0, 0)
+    base["sites"] = []
+    pair = [synth.jitter_copy(base, s) for s in (3, 4)]
+    b = synth.assemble([base] * 32, 2, (-0.2,), (7.0,), (300.0,), (synth.DIM_H,), per_replica=pair * 32,
+                       H_scale=lams, dt=0.0, mc_every=0, ex_every=1)
+    off = b["atom_off"]
+    E = [oracle.energy(b["xyz"][off[r]:off[r + 1]], b["q"][off[r]:off[r + 1]], b["rho"][off[r]:off[r + 1]],
+                       b["screen"][off[r]:off[r + 1]], b["sigma"][off[r]:off[r + 1]], b["eps"][off[r]:off[r + 1]]).sum()
+         for r in (0, 1)]
+    t = [oracle.tether(b["xyz"][off[r]:off[r + 1]], b["x0"][off[r]:off[r + 1]], b["k_tether"])[0] for r in (0, 1)]
+    U = lambda r, lam: lam * E[r] + t[r]
+    beta = 1.0 / (oracle.constants()["kB"] * 300.0)
+    eA, eB = -beta * (U(0, lams[0]) + U(1, lams[1])), -beta * (U(0, lams[1]) + U(1, lams[0]))
+    pA = 1.0 / (1.0 + math.exp(eB - eA))
+    ctx = Context(off)
+    d = DeviceBatch.from_numpy(b)
+    md = MD(ctx, d, b, seed=77)
+    md.run(1, init_forces=True)
+    n = 400
+    held = np.zeros((n, 32))
+    for k in range(n):
+        md.run(1)
+        held[k] = d.t["target_idx"].cpu().numpy().reshape(-1, 4)[0::2, synth.DIM_H] == 0
+    ctx.check()
+    ctx.close()
+    per_pair = held.mean(0)                     # 32 independent chains
+    assert abs(per_pair.mean() - pA) <= batch_mean_bound(per_pair, 16), (per_pair.mean(), pA)
+
+
 def test_replica_grid_md_with_exchanges_matches_oracle():
     """A 2 x 2 x 2 (E, T, pH) grid, 2 instances, MC every 5 steps and
     exchanges every 10: targets and states follow the oracle exactly."""
