@@ -162,8 +162,10 @@ typedef struct {
 /* Create a context for one batch layout on the current HIP device.
  * atom_off_host: HOST array [n_rep+1], atom_off[0] = 0, non-decreasing, every
  * replica with at least 1 atom; 1 <= n_rep < 2^26.  Allocates the workspace (a few int64/float per
- * atom plus the pair work lists).  Errors: GBR_E_INVAL, GBR_E_NODEVICE,
- * GBR_E_NOMEM, GBR_E_HIP. */
+ * atom plus the pair work lists; with both cutoffs set also the packed lists,
+ * up to 2 x 256 bytes per later tile of every I block and blocking, which the
+ * pair passes rebuild from the positions at every evaluation).  Errors:
+ * GBR_E_INVAL, GBR_E_NODEVICE, GBR_E_NOMEM, GBR_E_HIP. */
 int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
                    const int32_t* atom_off_host);
 

@@ -70,7 +70,7 @@ CONFIGS = {
     4: Workload("c4_uneven_64sys", (500, 20000), 4, 64, -1, -1, (-0.2,), (5.0, 6.0, 7.0, 8.0),
                 (300.0,), (DIM_PH,), 0, 10, 100, False, 1004, 2004),
     # beyond the all-pairs regime: salt and cutoffs on one large system whose
-    # atoms come in compact 64-atom blocks (the pair passes cull distant tiles)
+    # atoms come in compact 64-atom blocks (the pair passes pack the atoms near each block)
     5: Workload("c5_salt_cutoff_1x100k", (100000,), 1, 1, -1, -1, (-0.2,), (7.0,), (300.0,), (DIM_E,),
                 0, 10, 0, False, 1005, 2005,
                 extra={"kappa": 0.1, "cut": 12.0, "rgbmax": 15.0, "blocked": True}),
