@@ -125,8 +125,8 @@ int upload(void* dst, const void* src, size_t bytes) {
 // One force evaluation inside md_step (the caller has cleared the accumulators);
 // advance: the evaluation belongs to a step, whose counter then advances.
 int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, bool advance, hipStream_t s) {
-    hipError_t e = launch_cull(c, a.st.xyz, s);
-    if (e != hipSuccess) return hip_fail(e, "cull");
+    hipError_t e = launch_pack(c, a.st.xyz, s);
+    if (e != hipSuccess) return hip_fail(e, "pack");
     {
         Timed t(c, GBR_K_BORN_PAIR, s, true);
         e = launch_born_pair(c, a.st.xyz, a.pr.rho, a.pr.screen, s, t.ev);
@@ -307,9 +307,9 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
             (rc = upload(c->lists[k].items, items.data(), sizeof(int2) * items.size())))
             return done(rc);
     }
-    // with both cutoffs the pair passes run culled copies of the lists
-    c->cull = p.cut > 0 && p.rgbmax > 0;
-    if (c->cull) {
+    // with both cutoffs the pair passes run packed lists
+    c->packed = p.cut > 0 && p.rgbmax > 0;
+    if (c->packed) {
         std::vector<int32_t> tb(n_rep);
         for (int r = 0, t = 0; r < n_rep; ++r) {
             tb[r] = t;
@@ -318,7 +318,7 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
         if ((rc = dev_alloc(&c->tile_base, n_rep))) return done(rc);
         if ((rc = upload(c->tile_base, tb.data(), sizeof(int32_t) * n_rep))) return done(rc);
         if ((rc = dev_alloc(&c->tile_box, 2 * (size_t)c->n_tiles))) return done(rc);
-        if ((rc = dev_alloc(&c->cull_count, 8))) return done(rc);
+        if ((rc = dev_alloc(&c->pack_count, 8))) return done(rc);
         std::vector<gbr::PairItem> intra, iblocks;
         std::vector<int32_t> p0;
         std::vector<gbr::PackWindow> wins;
@@ -345,12 +345,12 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
                 if ((rc = dev_alloc(&L.blk_count[v], iblocks.size()))) return done(rc);
                 if (hipMemset(L.blk_count[v], 0, sizeof(int32_t) * std::max<size_t>(iblocks.size(), 1)) != hipSuccess)
                     return done(fail(GBR_E_HIP, "clearing the packing counts"));
-                if ((rc = dev_alloc(&L.culled[v], (size_t)(L.n_intra + cap)))) return done(rc);
-                if (!intra.empty() && (rc = upload(L.culled[v], intra.data(), sizeof(int2) * intra.size())))
+                if ((rc = dev_alloc(&L.run[v], (size_t)(L.n_intra + cap)))) return done(rc);
+                if (!intra.empty() && (rc = upload(L.run[v], intra.data(), sizeof(int2) * intra.size())))
                     return done(rc);
                 if ((rc = dev_alloc(&L.pk_hdr[v], std::max<size_t>((size_t)cap, 1)))) return done(rc);
                 if ((rc = dev_alloc(&L.pk_j[v], std::max<size_t>((size_t)cap * 64, 1)))) return done(rc);
-                L.n_culled[v] = c->cull_count + 2 * k + v;
+                L.n_run[v] = c->pack_count + 2 * k + v;
             }
         }
     }
@@ -396,13 +396,13 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     for (auto& L : c->lists) {
         (void)hipFree(L.items); (void)hipFree(L.iblk); (void)hipFree(L.blk_p0); (void)hipFree(L.win);
         for (int v = 0; v < 2; ++v) {
-            (void)hipFree(L.culled[v]); (void)hipFree(L.blk_count[v]); (void)hipFree(L.pk_hdr[v]);
+            (void)hipFree(L.run[v]); (void)hipFree(L.blk_count[v]); (void)hipFree(L.pk_hdr[v]);
             (void)hipFree(L.pk_j[v]);
         }
     }
     (void)hipFree(c->tile_base);
     (void)hipFree(c->tile_box);
-    (void)hipFree(c->cull_count);
+    (void)hipFree(c->pack_count);
     (void)hipFree(c->psi_fx); (void)hipFree(c->dEdR_fx); (void)hipFree(c->dEdR); (void)hipFree(c->chain_c);
     (void)hipFree(c->ke_fx); (void)hipFree(c->ex_nH); (void)hipFree(c->ex_ne); (void)hipFree(c->ex_eps);
     (void)hipFree(c->ex_vscale); (void)hipFree(c->ex_enb); (void)hipFree(c->ex_fscale);
@@ -487,7 +487,7 @@ int gb_born_radii(gbr_ctx* c, const float* xyz, const float* rho, const float* s
                   float* dRdpsi, double* psi, hipStream_t s) {
     if (int rc = check_ctx(c)) return rc;
     REQ(xyz); REQ(rho); REQ(screen); REQ(R); REQ(dRdpsi);
-    hipError_t e = launch_cull(c, xyz, s);
+    hipError_t e = launch_pack(c, xyz, s);
     if (e == hipSuccess) e = launch_zero_i64(c->psi_fx, c->n_atoms, s);
     if (e != hipSuccess) return hip_fail(e, "zero");
     {
@@ -525,7 +525,7 @@ int gb_energy_forces(gbr_ctx* c, const float* xyz, const float* q, const float* 
         if (e == hipSuccess && gr) e = launch_zero_i64(dEdrho_fx, N, s);
     }
     if (e == hipSuccess) e = launch_zero_i64(c->dEdR_fx, N, s);
-    if (e == hipSuccess) e = launch_cull(c, xyz, s);
+    if (e == hipSuccess) e = launch_pack(c, xyz, s);
     if (e != hipSuccess) return hip_fail(e, "zero");
     {
         Timed t(c, GBR_K_ENERGY_PAIR, s, true);

@@ -21,8 +21,8 @@ struct PairList {
     // (radius rgbmax, [0]) and for the energy pass (cut, [1]): the n_intra
     // items whose pairs lie inside one I block (a fixed prefix), then the
     // packed items of the current positions
-    int2* culled[2] = {nullptr, nullptr};
-    int32_t* n_culled[2] = {nullptr, nullptr};   // their counts (device)
+    int2* run[2] = {nullptr, nullptr};
+    int32_t* n_run[2] = {nullptr, nullptr};      // their counts (device)
     int32_t n_intra = 0;
     int2* iblk = nullptr;                        // I blocks {rep, A} with tiles after them
     int32_t* blk_p0 = nullptr;                   // [n_iblk] each block's first packed tile
@@ -62,10 +62,10 @@ struct gbr_ctx {
     int2* tiles = nullptr;           // per-atom tiles {rep, tile}
     int32_t n_tiles = 0;
     gbr::PairList lists[4];          // NI = 1, 2, 4, 8
-    bool cull = false;               // both cutoffs set: the pair passes run culled lists
+    bool packed = false;             // both cutoffs set: the pair passes run packed lists
     int32_t* tile_base = nullptr;    // [n_rep] index of each replica's first tile
     float4* tile_box = nullptr;      // [2 n_tiles] per-tile bounding boxes (min, max)
-    int32_t* cull_count = nullptr;   // [8] items per list and radius
+    int32_t* pack_count = nullptr;   // [8] items per list and radius
     int ni_born = 4, ni_energy = 4, ni_chain = 4;
     gbr::LaunchShape shape;
     // workspace
@@ -118,7 +118,7 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
 // use and every I block the atoms after the block that come within rgbmax
 // (for the descreening passes) or cut (for the energy pass) of its box,
 // packed into items after the list's intra-block items.
-hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s);
+hipError_t launch_pack(const gbr_ctx* c, const float* xyz, hipStream_t s);
 
 // per-atom kernels ------------------------------------------------------------
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);

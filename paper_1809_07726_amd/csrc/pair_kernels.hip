@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_born_pair(
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
-    if (n_dev) n_items = n_dev[0];                // a culled list: its device count
+    if (n_dev) n_items = n_dev[0];                // a packed list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
         const ItemGeom g = item_geom<NI, EXT>(items[it], atom_off, ext);
         float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], s2i[NI], s3i[NI], mi[NI], sxi[NI], acc[NI];
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     const float lc = 0.60056120439322491f;       // sqrt(log2(e) / 4)
     const float hl = 0.5f / LOG2E;               // D = D2 / log2(e)
     const float wq = -0.25f * taup;
-    if (n_dev) n_items = n_dev[0];                // a culled list: its device count
+    if (n_dev) n_items = n_dev[0];                // a packed list: its device count
     // energy sums of the wavefront's current replica (valid in lane 63); one
     // set of atomics per replica change rather than per item, so that the
     // items of one large replica do not all meet at its three energy slots
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
-    if (n_dev) n_items = n_dev[0];                // a culled list: its device count
+    if (n_dev) n_items = n_dev[0];                // a packed list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
         const ItemGeom g = item_geom<NI, EXT>(items[it], atom_off, ext);
         float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], ci[NI], Si[NI], mi[NI], sxi[NI], s2i[NI], s3i[NI];
@@ -928,8 +928,8 @@ static PairExt make_pair_ext(const gbr_ctx* c, const PairList& L, int kind) {
     e.ak = (float)(p.eps_in / p.eps_out * p.kappa);
     e.cut2 = p.cut > 0 ? (float)(p.cut * p.cut) : FLT_MAX;
     e.rgb2 = p.rgbmax > 0 ? (float)(p.rgbmax * p.rgbmax) : FLT_MAX;
-    e.pk_hdr = c->cull ? L.pk_hdr[kind] : nullptr;
-    e.pk_j = c->cull ? L.pk_j[kind] : nullptr;
+    e.pk_hdr = c->packed ? L.pk_hdr[kind] : nullptr;
+    e.pk_j = c->packed ? L.pk_j[kind] : nullptr;
     return e;
 }
 
@@ -937,13 +937,13 @@ static bool uses_ext(const gbr_ctx* c) {
     return c->prm.kappa > 0 || c->prm.cut > 0 || c->prm.rgbmax > 0;
 }
 
-hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s) {
-    if (!c->cull) return hipSuccess;
+hipError_t launch_pack(const gbr_ctx* c, const float* xyz, hipStream_t s) {
+    if (!c->packed) return hipSuccess;
     CountInit init;
     for (int k = 0; k < 4; ++k)
         for (int v = 0; v < 2; ++v) init.v[2 * k + v] = c->lists[k].n_intra;
     hipLaunchKernelGGL(k_tile_boxes, dim3((c->n_tiles + 3) / 4), dim3(256), 0, s, c->tiles, c->n_tiles,
-                       c->atom_off, c->n_atoms, xyz, c->tile_box, c->cull_count, init);
+                       c->atom_off, c->n_atoms, xyz, c->tile_box, c->pack_count, init);
     // the tile boxes' FP32 bounds are exact (min / max of the stored
     // coordinates); the margin covers the rounding of the kernels' own r^2
     const double rc[2] = {c->prm.rgbmax * (1.0 + 1e-5) + 1e-4, c->prm.cut * (1.0 + 1e-5) + 1e-4};
@@ -961,7 +961,7 @@ hipError_t launch_cull(const gbr_ctx* c, const float* xyz, hipStream_t s) {
                            L.ni, c->atom_off, c->tile_base, c->tile_box, xyz, c->n_atoms,
                            (float)(rc[v] * rc[v]), L.blk_count[v], L.pk_j[v]);
         hipLaunchKernelGGL(k_pack_items, dim3((L.n_iblk + 63) / 64), dim3(64), 0, s, L.iblk, L.blk_p0,
-                           L.n_iblk, L.blk_count[v], L.culled[v], L.n_culled[v], L.pk_hdr[v]);
+                           L.n_iblk, L.blk_count[v], L.run[v], L.n_run[v], L.pk_hdr[v]);
     }
     return hipGetLastError();
 }
@@ -972,8 +972,8 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
     const PairList& L = list_for(c, c->ni_born);
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
-    const int2* items = c->cull ? L.culled[0] : L.items;
-    const int32_t* n_dev = c->cull ? L.n_culled[0] : nullptr;
+    const int2* items = c->packed ? L.run[0] : L.items;
+    const int32_t* n_dev = c->packed ? L.n_run[0] : nullptr;
     const float off = (float)c->prm.offset;
     const PairExt pe = make_pair_ext(c, L, 0);
     const bool ext = uses_ext(c);
@@ -997,8 +997,8 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     const PairList& L = list_for(c, c->ni_energy);
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
-    const int2* items = c->cull ? L.culled[1] : L.items;
-    const int32_t* n_dev = c->cull ? L.n_culled[1] : nullptr;
+    const int2* items = c->packed ? L.run[1] : L.items;
+    const int32_t* n_dev = c->packed ? L.n_run[1] : nullptr;
     const float sq = (float)sqrt(c->prm.k_e / c->prm.eps_in);
     const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
     const PairExt pe = make_pair_ext(c, L, 1);
@@ -1025,8 +1025,8 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
     const PairList& L = list_for(c, c->ni_chain);
     if (L.n_items == 0) return no_launch(s, ev);
     dim3 grid(grid_for(c, L.n_items)), block(64 * c->shape.waves_per_group);
-    const int2* items = c->cull ? L.culled[0] : L.items;
-    const int32_t* n_dev = c->cull ? L.n_culled[0] : nullptr;
+    const int2* items = c->packed ? L.run[0] : L.items;
+    const int32_t* n_dev = c->packed ? L.n_run[0] : nullptr;
     const float off = (float)c->prm.offset;
     const PairExt pe = make_pair_ext(c, L, 0);
 #define GBR_CH(NI, RH, EX) hipExtLaunchKernelGGL((k_chain_pair<NI, RH, EX>), grid, block, 0, s, ev.start, \

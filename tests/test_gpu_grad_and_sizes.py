@@ -140,9 +140,9 @@ def test_full_size_uneven_batch_sampled_and_deterministic():
     assert np.all(E == E[:, :1])
 
 
-def test_blocked_20k_system_with_salt_and_culled_cutoffs_matches_oracle():
+def test_blocked_20k_system_with_salt_and_packed_cutoff_lists_matches_oracle():
     """One 20,000-atom system in compact 64-atom blocks with salt and both
-    cutoffs, so that the pair passes run culled work lists: energies, Born
+    cutoffs, so that the pair passes run packed work lists: energies, Born
     radii and forces against the oracle.  The atoms sit exactly on the 3.0 A
     lattice (no jitter), so every pair distance squared is a multiple of 9 A^2
     and cut = 12.1 A, rgbmax = 15.1 A lie far from any of them (no pair sits
