@@ -64,9 +64,15 @@ __device__ __forceinline__ int logical_wave() {
 }
 
 // acc <- acc[lane + 1 (mod 64)] + c : rotate-and-add, one VALU instruction.
+// The rotation gives every lane a source, so the DPP "old" value is never
+// used.  SELF passes acc itself as old, which lets the destination reuse
+// acc's register instead of a zeroed copy; which form schedules better
+// differs by kernel (measured on the loop bodies).
+template <bool SELF = false>
 __device__ __forceinline__ float rot_add(float acc, float c) {
+    const int a = __builtin_bit_cast(int, acc);
     return c + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-                   0, __builtin_bit_cast(int, acc), 0x134 /* wave_rol:1 */, 0xF, 0xF, false));
+                   SELF ? a : 0, a, 0x134 /* wave_rol:1 */, 0xF, 0xF, false));
 }
 
 __device__ __forceinline__ void wave_lds_fence() {
@@ -469,11 +475,11 @@ __global__ __launch_bounds__(256) void k_energy_pair(
             }
         };
         auto rotate = [&](EnergyJ& a, const EnergyJ& c) {
-            a.x = rot_add(a.x, c.x);
-            a.y = rot_add(a.y, c.y);
-            a.z = rot_add(a.z, c.z);
-            a.R = rot_add(a.R, c.R);
-            if (GQ) a.q = rot_add(a.q, c.q);
+            a.x = rot_add<EXT>(a.x, c.x);
+            a.y = rot_add<EXT>(a.y, c.y);
+            a.z = rot_add<EXT>(a.z, c.z);
+            a.R = rot_add<EXT>(a.R, c.R);
+            if (GQ) a.q = rot_add<EXT>(a.q, c.q);
         };
         auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
@@ -645,10 +651,10 @@ __global__ __launch_bounds__(256) void k_chain_pair(
             }
         };
         auto rotate = [&](ChainJ& a, const ChainJ& c) {
-            a.x = rot_add(a.x, c.x);
-            a.y = rot_add(a.y, c.y);
-            a.z = rot_add(a.z, c.z);
-            if (RHO) a.r = rot_add(a.r, c.r);
+            a.x = rot_add<EXT>(a.x, c.x);
+            a.y = rot_add<EXT>(a.y, c.y);
+            a.z = rot_add<EXT>(a.z, c.z);
+            if (RHO) a.r = rot_add<EXT>(a.r, c.r);
         };
         auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
