@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_born_finalize(
 // without salt): dE/dR_i = pair part - (1/2) q_i^2 kg'(R_i);
 // c_i = dE/dR_i * dR_i/dpsi_i * rho~_i/2; E_GB self = -(1/2) q_i^2 kg(R_i) added
 // to the replica's energy; dE/dq_i self = -q_i kg(R_i).
-__global__ __launch_bounds__(256) void k_coef(
+__global__ __launch_bounds__(512) void k_coef(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
     const float* __restrict__ q, const float* __restrict__ rho, const float* __restrict__ R,
     const float* __restrict__ dRdpsi, const int64_t* __restrict__ dEdR_fx, double ketau,
@@ -60,18 +60,14 @@ __global__ __launch_bounds__(256) void k_coef(
     int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint64_t* __restrict__ step,
     uint32_t* __restrict__ err)
 {
-    const int w = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     const int lane = threadIdx.x & 63;
     // inside md_step: the step counter advances here, once per step (nothing in
     // this kernel reads it; the next step's kernels and the exchange do)
-    if (step && w == 0 && lane == 0) step[0] = step[0] + 1;
-    // TILES_PER_WAVE consecutive tiles per wavefront; the self energies of
-    // those in one replica go out in one atomic
-    int cur = -1;
-    long long esum = 0;
-    for (int i = 0; i < TILES_PER_WAVE; ++i) {
-        const int t = w * TILES_PER_WAVE + i;
-        if (t >= n_tiles) break;
+    if (step && t == 0 && lane == 0) step[0] = step[0] + 1;
+    int rep = -1;
+    long long v[1] = {0};
+    if (t < n_tiles) {
         const int2 tl = tiles[t];
         const int a0 = atom_off[tl.x], n = atom_off[tl.x + 1] - a0;
         const int li = tl.y * 64 + lane;
@@ -91,15 +87,10 @@ __global__ __launch_bounds__(256) void k_coef(
             eself = -0.5 * qa * qa * kg;
             if (dEdq_fx) dEdq_fx[a] += to_fixed(-qa * kg, FX_FORCE, err);
         }
-        const long long fx = to_fixed(wave_sum_d(eself), FX_ENERGY, err);
-        if (tl.x != cur) {
-            if (cur >= 0 && lane == 0) atomic_add_fx(&energy_fx[4 * cur], esum);
-            cur = tl.x;
-            esum = 0;
-        }
-        esum += fx;
+        rep = tl.x;
+        v[0] = to_fixed(wave_sum_d(eself), FX_ENERGY, err);
     }
-    if (cur >= 0 && lane == 0) atomic_add_fx(&energy_fx[4 * cur], esum);
+    if (group_runs_by_replica<1>(rep, v)) atomic_add_fx(&energy_fx[4 * rep], v[0]);
 }
 
 // per-atom part of dE/drho_i: dE/dR_i [R^2 (1/rho~^2 - tanh/rho^2) + dR/dpsi * psi/rho~]
@@ -189,8 +180,7 @@ hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const
                        const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, uint64_t* step,
                        hipStream_t s) {
     const GBConstH k = make_const(c->prm);
-    const int waves = (c->n_tiles + TILES_PER_WAVE - 1) / TILES_PER_WAVE;
-    hipLaunchKernelGGL(k_coef, dim3((waves + 3) / 4), dim3(256), 0, s, c->tiles, c->n_tiles,
+    hipLaunchKernelGGL(k_coef, dim3((c->n_tiles + 7) / 8), dim3(512), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, q, rho, R, dRdpsi, c->dEdR_fx, k.ke_d * k.tau_d,
                        c->prm.k_e / c->prm.eps_out, c->prm.kappa, c->prm.offset,
                        c->dEdR, c->chain_c, energy_fx, dEdq_fx, step, c->err);

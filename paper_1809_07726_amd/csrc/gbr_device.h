@@ -27,9 +27,7 @@ constexpr float FXF_ENERGY = 4294967296.0f;
 
 enum Stream : uint32_t { STREAM_O = 1, STREAM_MCPH = 2, STREAM_MCRED = 3, STREAM_EX = 4 };
 
-// Per-tile kernels that sum per-replica energies take this many consecutive
-// tiles per wavefront and send one atomic per replica they meet.
-constexpr int TILES_PER_WAVE = 4;
+
 
 // ------------------------------------------------------------ fixed point
 __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t bits) {
@@ -110,6 +108,29 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     // doubles: butterfly through shuffles (used only once per tile)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, GBR_WAVE);
     return v;
+}
+
+// Per-tile kernels sum per-replica values wavefront by wavefront (one tile
+// each); this merges the wavefronts of one workgroup: every run of
+// consecutive wavefronts of one replica (rep; rep < 0: nothing) is added into
+// the run's first wavefront, whose lane 0 returns true with the run's totals
+// in v, so that one large replica's tiles do not all meet at its slots in
+// memory.  Every thread of the workgroup calls it (at most 16 wavefronts).
+constexpr int MAX_GROUP_WAVES = 16;
+template <int NV>
+__device__ __forceinline__ bool group_runs_by_replica(int rep, long long (&v)[NV]) {
+    __shared__ int s_rep[MAX_GROUP_WAVES];
+    __shared__ long long s_v[NV][MAX_GROUP_WAVES];
+    const int w = (int)(threadIdx.x >> 6), nw = (int)(blockDim.x >> 6), lane = threadIdx.x & 63;
+    if (lane == 0) {
+        s_rep[w] = rep;
+        for (int k = 0; k < NV; ++k) s_v[k][w] = v[k];
+    }
+    __syncthreads();
+    if (lane != 0 || rep < 0 || (w > 0 && s_rep[w - 1] == rep)) return false;
+    for (int u = w + 1; u < nw && s_rep[u] == rep; ++u)
+        for (int k = 0; k < NV; ++k) v[k] += s_v[k][u];
+    return true;
 }
 
 // -------------------------------------------------- Philox4x32-10 (SC'11)

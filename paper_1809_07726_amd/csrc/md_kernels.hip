@@ -94,31 +94,22 @@ __global__ __launch_bounds__(256) void k_md_first(
 
 // The pair forces scaled by the replica's Hamiltonian scale, plus the tether
 // k |x - x0|^2 (its energy in the replica's slot 3); then (kick) v += dt/2 F/m
-// and the kinetic energy.  TILES_PER_WAVE tiles per wavefront.
-__global__ __launch_bounds__(256) void k_md_last(
+// and the kinetic energy; one tile per wavefront, eight per workgroup.
+__global__ __launch_bounds__(512) void k_md_last(
     const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
     int ntot, double hdt, double k_t, const double* __restrict__ H_scale,
     const int32_t* __restrict__ target_idx, const float* __restrict__ mass,
-    const float* __restrict__ x0, const float* __restrict__ xyz, float* __restrict__ v,
+    const float* __restrict__ x0, const float* __restrict__ xyz, float* __restrict__ vel,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ energy_fx, int64_t* __restrict__ ke_fx,
     int kick, uint32_t* __restrict__ err)
 {
-    const int w = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     const int lane = threadIdx.x & 63;
-    int cur = -1;
-    long long se_sum = 0, sk_sum = 0;
-    auto flush = [&]() {
-        if (cur >= 0 && lane == 0) {
-            atomic_add_fx(&energy_fx[4 * cur + 3], se_sum);
-            atomic_add_fx(&ke_fx[cur], sk_sum);
-        }
-        se_sum = sk_sum = 0;
-    };
-    for (int i = 0; i < TILES_PER_WAVE; ++i) {
-        const int t = w * TILES_PER_WAVE + i;
-        if (t >= n_tiles) break;
+    int rep = -1;
+    long long v[2] = {0, 0};
+    if (t < n_tiles) {
         const int2 tl = tiles[t];
-        const int rep = tl.x;
+        rep = tl.x;
         const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
         const int li = tl.y * 64 + lane;
         double et = 0.0, kin = 0.0;
@@ -133,24 +124,21 @@ __global__ __launch_bounds__(256) void k_md_last(
                 et += k_t * dx * dx;
                 const int64_t f = scale_fx(force_fx[idx], lam, err) + to_fixed(-2.0 * k_t * dx, FX_FORCE, err);
                 force_fx[idx] = f;
-                double vv = v[idx];
+                double vv = vel[idx];
                 if (kick) {
                     vv += hdt * from_fixed(f, INV_FX_FORCE) * im;
-                    v[idx] = (float)vv;
+                    vel[idx] = (float)vv;
                 }
                 kin += 0.5 * m * (double)(float)vv * (double)(float)vv / ACC_CONV;
             }
         }
-        const long long se = to_fixed(wave_sum_d(et), FX_ENERGY, err);
-        const long long sk = to_fixed(wave_sum_d(kin), FX_ENERGY, err);
-        if (rep != cur) {
-            flush();
-            cur = rep;
-        }
-        se_sum += se;
-        sk_sum += sk;
+        v[0] = to_fixed(wave_sum_d(et), FX_ENERGY, err);
+        v[1] = to_fixed(wave_sum_d(kin), FX_ENERGY, err);
     }
-    flush();
+    if (group_runs_by_replica<2>(rep, v)) {
+        atomic_add_fx(&energy_fx[4 * rep + 3], v[0]);
+        atomic_add_fx(&ke_fx[rep], v[1]);
+    }
 }
 
 __global__ void k_ke_out(int n_rep, const int64_t* __restrict__ ke_fx, double* __restrict__ ke) {
@@ -631,8 +619,7 @@ hipError_t launch_md_first(const gbr_ctx* c, const MDArgs& a, bool mid, hipStrea
 }
 
 hipError_t launch_md_last(const gbr_ctx* c, const MDArgs& a, int kick, hipStream_t s) {
-    const int waves = (c->n_tiles + TILES_PER_WAVE - 1) / TILES_PER_WAVE;
-    hipLaunchKernelGGL(k_md_last, dim3((waves + 3) / 4), dim3(256), 0, s, c->tiles, c->n_tiles,
+    hipLaunchKernelGGL(k_md_last, dim3((c->n_tiles + 7) / 8), dim3(512), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, c->n_atoms, 0.5 * a.pr.dt, a.pr.k_tether, a.pr.grid.H_scale,
                        a.st.target_idx, a.pr.mass, a.pr.x0, a.st.xyz, a.st.v, a.st.force_fx, a.st.energy_fx, c->ke_fx,
                        kick, c->err);

@@ -880,19 +880,17 @@ __global__ __launch_bounds__(64) void k_pack_items(
         ib = iblk[w];
         p0 = blk_p0[w];
     }
-    // the wavefront's items in round-robin order over its blocks (the p-th
-    // item of every block, then the (p+1)-th): items next to each other in
-    // the list run at the same time and should not flush into the same I atoms
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int off = 0;
-    for (int p = 0;; ++p) {
-        const unsigned long long act = __ballot(nt > p);
-        if (!act) break;
-        if (nt > p) {
-            items[base + off + __popcll(act & below)] = make_int2(ib.x | (ITEM_PACKED << 30), p0 + p);
-            pk_hdr[p0 + p] = (ib.y << 7) | min(64, cnt - 64 * p);
+    // the wavefront writes block L's items together, block by block
+    for (int L = 0; L < 64; ++L) {
+        const int ntL = __shfl(nt, L, 64);
+        if (ntL == 0) continue;
+        const int slot0 = base + __shfl(pre, L, 64) - ntL;
+        const int cntL = __shfl(cnt, L, 64), repL = __shfl(ib.x, L, 64), AL = __shfl(ib.y, L, 64);
+        const int p0L = __shfl(p0, L, 64);
+        for (int p = lane; p < ntL; p += 64) {
+            items[slot0 + p] = make_int2(repL | (ITEM_PACKED << 30), p0L + p);
+            pk_hdr[p0L + p] = (AL << 7) | min(64, cntL - 64 * p);
         }
-        off += __popcll(act);
     }
 }
 
