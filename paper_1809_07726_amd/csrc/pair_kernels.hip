@@ -757,7 +757,7 @@ __global__ __launch_bounds__(256) void k_tile_boxes(
 // Packing, in two passes.  Every I block (rep, A) with tiles after it owns
 // the packed tiles P0 .. P0 + (T - t1) - 1 (t1: the first tile after the
 // block), as many as it has tiles after it, and their 64 J slots each.
-//  k_pack_atoms: one wavefront per window of up to 64 tiles after a block;
+//  k_pack_atoms: one wavefront per window of up to PACK_WINDOW tiles after a block;
 //    the tiles whose box comes within rc of the block's box, then their atoms
 //    within rc of it, appended to the block's slots (one atomic per window on
 //    the block's atom count; the windows' atoms land in arbitrary order).
@@ -783,8 +783,8 @@ __global__ __launch_bounds__(256) void k_pack_atoms(
     const float4* __restrict__ box, const float* __restrict__ xyz, int ntot, float rc2,
     int32_t* __restrict__ blk_count, int32_t* __restrict__ pk_j)
 {
-    __shared__ unsigned long long s_mask[MAXW][64];
-    __shared__ int s_tile[MAXW][64];
+    __shared__ unsigned long long s_mask[MAXW][PACK_WINDOW];
+    __shared__ int s_tile[MAXW][PACK_WINDOW];
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int wi = blockIdx.x * (blockDim.x >> 6) + wv;
     if (wi >= n_win) return;
@@ -800,25 +800,41 @@ __global__ __launch_bounds__(256) void k_pack_atoms(
         lo = make_float4(fminf(lo.x, l.x), fminf(lo.y, l.y), fminf(lo.z, l.z), 0.0f);
         hi = make_float4(fmaxf(hi.x, h.x), fmaxf(hi.y, h.y), fmaxf(hi.z, h.z), 0.0f);
     }
-    const int t = c0 + lane;
-    bool near = false;
-    if (t < T) near = box_gap2(lo, hi, box[2 * (tb + t)], box[2 * (tb + t) + 1]) < rc2;
-    unsigned long long nm = __ballot(near);
-    if (!nm) return;
+    // the window's tiles, 64 to a ballot word (lane l of word q: tile c0 + 64 q + l)
+    constexpr int NQ = (PACK_WINDOW + 63) / 64;
+    unsigned long long nmq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int t = c0 + 64 * q + lane;
+        bool near = false;
+        if (64 * q + lane < PACK_WINDOW && t < T)
+            near = box_gap2(lo, hi, box[2 * (tb + t)], box[2 * (tb + t) + 1]) < rc2;
+        nmq[q] = __ballot(near);
+    }
     int nn = 0, total = 0;
-    while (nm) {
+    int q = 0;
+    unsigned long long nm = nmq[0];
+    auto next_tile = [&]() -> int {                // next near tile of the window, or -1
+        while (!nm && q + 1 < NQ) nm = nmq[++q];
+        if (!nm) return -1;
+        const int b = c0 + 64 * q + __ffsll((long long)nm) - 1;
+        nm &= nm - 1ull;
+        return b;
+    };
+    for (;;) {
         int bt[PACK_BATCH];
         float x[PACK_BATCH], y[PACK_BATCH], z[PACK_BATCH];
+        bool any = false;
 #pragma unroll
         for (int k = 0; k < PACK_BATCH; ++k) {
-            bt[k] = -1;
-            if (nm) {
-                bt[k] = c0 + __ffsll((long long)nm) - 1;
-                nm &= nm - 1ull;
+            bt[k] = next_tile();
+            if (bt[k] >= 0) {
+                any = true;
                 const int jl = min(bt[k] * 64 + lane, n - 1);
                 x[k] = xyz[a0 + jl]; y[k] = xyz[ntot + a0 + jl]; z[k] = xyz[2 * ntot + a0 + jl];
             }
         }
+        if (!any) break;
 #pragma unroll
         for (int k = 0; k < PACK_BATCH; ++k) {
             if (bt[k] < 0) break;

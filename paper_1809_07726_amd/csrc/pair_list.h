@@ -131,8 +131,11 @@ inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vec
 // 64 at a time on the device at every evaluation.  The fixed part: the items
 // whose pairs lie inside one I block (in list order); the I blocks {rep, A}
 // with tiles after them, each owning as many packed tiles (from p0 on) as it
-// has tiles after it (cap in all); and the windows of up to 64 of those tiles
-// that the packing scans, {block, A << 16 | first tile, block's p0, replica}.
+// has tiles after it (cap in all); and the windows of up to PACK_WINDOW of
+// those tiles that the packing scans, {block, A << 16 | first tile, block's
+// p0, replica}.
+constexpr int32_t PACK_WINDOW = 64;
+
 struct PackWindow {
     int32_t blk, a_c0, p0, rep;
 };
@@ -159,7 +162,7 @@ inline void build_packed_parts(const int32_t* off, int32_t n_rep, int ni,
             const int32_t blk = (int32_t)iblocks.size();
             iblocks.push_back(PairItem{r, a});
             p0.push_back((int32_t)cap);
-            for (int32_t c0 = t1; c0 < T; c0 += 64)
+            for (int32_t c0 = t1; c0 < T; c0 += PACK_WINDOW)
                 windows.push_back(PackWindow{blk, (a << 16) | c0, (int32_t)cap, r});
             cap += T - t1;
         }
