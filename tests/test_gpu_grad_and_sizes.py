@@ -162,3 +162,35 @@ def test_blocked_20k_system_with_salt_and_packed_cutoff_lists_matches_oracle():
     assert rms_rel(g["F"], -gx) < F_TOL
     _any_size_properties(b, g)
     assert n == b["atom_off"][-1]
+
+
+def test_full_size_100k_salt_cutoff_system_in_the_tuned_launch_sampled():
+    """The 100,000-atom salt-and-cutoff system at its full size, in the
+    launch the benchmark times (4 wavefronts x 8 workgroups per CU, one i
+    atom per lane in every pass, packed lists), with the atoms exactly on the
+    lattice (cut = 12.1 A, rgbmax = 15.1 A clear of every pair distance).
+    Sampled against the oracle on exact subsystems (the locality of the cut-off
+    sums is pinned on the CPU): the Born radii of 256 atoms (the atoms within
+    rgbmax + 1 A) and the forces on 24 atoms (within cut + 2 rgbmax + 1 A)."""
+    import paper_1809_07726_amd._capi as A
+    b = synth.make_config(5)
+    b["xyz"] = b["x0"].copy()
+    cut, rgb = 12.1, 15.1
+    P = A.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    G = oracle.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    print("case: 1 x 100,000 atoms, blocking (1, 1, 1), launch (4, 8)", flush=True)
+    g = gpu_eval(b, params=P, blocking=(1, 1, 1), launch=(4, 8))
+    _any_size_properties(b, g)
+    x = b["xyz"].astype(np.float64)
+    rng = np.random.default_rng(100)
+    for i in rng.choice(len(x), 256, replace=False):
+        near = np.flatnonzero(((x - x[i]) ** 2).sum(1) < (rgb + 1.0) ** 2)
+        _, Rs, _ = oracle.born(x[near], b["rho"][near], b["screen"][near], G)
+        assert abs(g["R"][i] / Rs[int(np.searchsorted(near, i))] - 1) < 2e-6, i
+    F_rms = np.sqrt((g["F"] ** 2).sum(1).mean())
+    for i in rng.choice(len(x), 24, replace=False):
+        sel = np.flatnonzero(((x - x[i]) ** 2).sum(1) < (cut + 2 * rgb + 1.0) ** 2)
+        _, gs, _, _ = oracle.gradient(x[sel], b["q"][sel], b["rho"][sel], b["screen"][sel], b["sigma"][sel],
+                                      b["eps"][sel], G)
+        Fo = -gs[int(np.searchsorted(sel, i))]
+        assert np.linalg.norm(g["F"][i] - Fo) <= 1e-5 * max(np.linalg.norm(Fo), F_rms), (i, g["F"][i], Fo)

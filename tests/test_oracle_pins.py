@@ -657,6 +657,31 @@ def test_exchange_pairs_only_nearest_neighbours_sharing_other_targets():
             assert gr[g] == bb["grid_rep"][g2] and gr[g2] == bb["grid_rep"][g]
 
 
+def test_cutoff_forces_and_radii_are_local():
+    """With both cutoffs the Born radius of atom i depends only on the atoms
+    within rgbmax of it, and the force on i only on the atoms within
+    cut + 2 rgbmax (direct pairs within cut; their radii; the radii of the
+    atoms whose radii move with x_i and their partners' radii).  The oracle
+    on the subsystem of those atoms (plus 1 A) gives the full system's values
+    to rounding: the premise of the sampled full-size checks."""
+    b = synth.make_config(5, n_atoms=4000)
+    x = b["x0"].astype(np.float64)
+    cut, rgb = 6.1, 7.1
+    gb = oracle.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    E, gx, _, _ = oracle.gradient(x, b["q"], b["rho"], b["screen"], b["sigma"], b["eps"], gb)
+    _, R, _ = oracle.born(x, b["rho"], b["screen"], gb)
+    for i in (0, 1234, 2222, 3999):
+        sel = np.flatnonzero(((x - x[i]) ** 2).sum(1) < (cut + 2 * rgb + 1.0) ** 2)
+        assert sel.size < 0.7 * len(x)
+        k = int(np.searchsorted(sel, i))
+        _, gs, _, _ = oracle.gradient(x[sel], b["q"][sel], b["rho"][sel], b["screen"][sel], b["sigma"][sel],
+                                      b["eps"][sel], gb)
+        assert np.abs(gs[k] - gx[i]).max() <= 1e-10 * np.abs(gx[i]).max()
+        near = np.flatnonzero(((x - x[i]) ** 2).sum(1) < (rgb + 1.0) ** 2)
+        _, Rs, _ = oracle.born(x[near], b["rho"][near], b["screen"][near], gb)
+        assert abs(Rs[int(np.searchsorted(near, i))] / R[i] - 1) < 1e-13
+
+
 # ------------------------- P12b: the Hamiltonian dimension (H-REMD)
 def _ham_pair(seeds, H_scale, n_atoms=16, **md):
     """Two replicas of a 16-atom system in independently jittered geometries
