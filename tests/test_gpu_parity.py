@@ -184,6 +184,23 @@ def test_salt_and_cutoffs_match_oracle(ni, kappa, cut, rgb):
     assert np.abs(plain["E"] - o["E"]).max() > 1e-3
 
 
+@pytest.mark.parametrize("ni", [1, 2, 4, 8])
+def test_ragged_uneven_replicas_with_packed_cutoff_lists(ni):
+    """Replica sizes from one atom to several 64-atom tiles (ragged tails,
+    blocks with and without tiles after them) in one batch with salt and both
+    cutoffs, so that every blocking's packed lists span replicas of every
+    shape."""
+    import paper_1809_07726_amd._capi as A
+    sizes = [1, 2, 37, 64, 65, 130, 257, 520, 700, 1300]
+    systems = [synth.draw_system(n, 900 + n, 1 if n >= 16 else 0, 1 if n >= 16 else 0, blocked=n >= 64)
+               for n in sizes]
+    b = synth.assemble(systems, 1, (-0.2,), (7.0,), (300.0,), (0,))
+    cut, rgb = clear_cutoffs(b, 8.0, 10.0)
+    P = A.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    G = oracle.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    _check(b, gpu_eval(b, True, True, blocking=(ni, ni, ni), params=P), _oracle_batch(b, gb=G), grads=True)
+
+
 def test_titration_delta_e_with_salt_and_cutoff_matches_oracle():
     import paper_1809_07726_amd._capi as A
     import torch
