@@ -65,3 +65,46 @@ def test_saturating_charge_sets_the_overflow_bit(setup):
     rc, bits = _check(ctx)
     assert rc == A.GBR_E_NUMERIC and bits & A.ERR_OVERFLOW and not bits & A.ERR_NONFINITE, (rc, bits)
     assert _check(ctx) == (A.GBR_OK, 0)
+
+
+def test_grid_validation_of_the_hamiltonian_dimension():
+    """md_step and remd_exchange reject a grid whose sizes do not multiply to
+    the replica count, nHam > 1 without scales, and dimension codes out of
+    range, before launching anything."""
+    import torch
+    import paper_1809_07726_amd._capi as A
+    from paper_1809_07726_amd import synth
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch
+    base = synth.draw_system(32, 5, 0, 0)
+    base["sites"] = []
+    b = synth.assemble([base], 4, (-0.2,), (7.0,), (300.0, 320.0), (synth.DIM_T, synth.DIM_H),
+                       H_scale=(1.0, 0.9), mc_every=0, ex_every=1)
+    ctx = Context(b["atom_off"])
+    d = DeviceBatch.from_numpy(b)
+    md = MD(ctx, d, b, seed=1)
+    md.run(1, init_forces=True)                       # the valid grid runs
+    g = md.pr.grid
+    bad = []
+    saved = (g.nHam, g.H_scale, g.n_dims, g.dim_order[1])
+    g.H_scale = None
+    bad.append(A.lib.md_step(ctx.h, C.byref(md.st), C.byref(md.pr), 1, 1, 1, 0, A.stream_handle()))
+    g.H_scale = saved[1]
+    g.nHam = 3
+    bad.append(A.lib.md_step(ctx.h, C.byref(md.st), C.byref(md.pr), 1, 1, 1, 0, A.stream_handle()))
+    g.nHam = saved[0]
+    g.dim_order[1] = 4
+    bad.append(A.lib.md_step(ctx.h, C.byref(md.st), C.byref(md.pr), 1, 1, 1, 0, A.stream_handle()))
+    g.dim_order[1] = saved[3]
+    g.n_dims = 5
+    bad.append(A.lib.md_step(ctx.h, C.byref(md.st), C.byref(md.pr), 1, 1, 1, 0, A.stream_handle()))
+    g.n_dims = saved[2]
+    assert bad == [A.GBR_E_INVAL] * 4, bad
+    R = ctx.n_rep
+    z = torch.zeros(R, dtype=torch.int32, device="cuda")
+    with pytest.raises(A.GBRError):                    # an H grid needs the nonbonded energies
+        ctx.remd_exchange(g, 1, z, z, torch.zeros(R, dtype=torch.float64, device="cuda"),
+                          d.t["target_idx"], d.t["grid_rep"], seed=1)
+    md.run(1)                                         # and the context still works
+    torch.cuda.synchronize()
+    assert _check(ctx) == (A.GBR_OK, 0)
+    ctx.close()
