@@ -174,6 +174,35 @@ def test_gpu_hamiltonian_exchange_samples_the_pair_boltzmann_weights():
     assert abs(per_pair.mean() - pA) <= batch_mean_bound(per_pair, 16), (per_pair.mean(), pA)
 
 
+def test_exchange_inputs_on_a_hamiltonian_grid():
+    """gbr_exchange_inputs on a 2 T x 3 H grid: enb is the unscaled
+    E_GB + E_C + E_LJ of each replica and the temperature-exchange energy is
+    that of the replica's own Hamiltonian, l (E_GB + E_C + E_LJ) + E_tether
+    (eps_mode 1), both as the oracle forms them from the same energies."""
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch
+    base = synth.draw_system(96, 4545, 1, 1)
+    reps = [synth.jitter_copy(base, 800 + r) for r in range(6)]
+    lams = (1.0, 0.85, 0.7)
+    b = synth.assemble([base], 6, (-0.2,), (7.0,), (300.0, 330.0), (synth.DIM_H, synth.DIM_T),
+                       per_replica=reps, H_scale=lams, mc_every=0, ex_every=0)
+    ctx = Context(b["atom_off"])
+    d = DeviceBatch.from_numpy(b)
+    md = MD(ctx, d, b, seed=3, eps_mode=1)
+    md.run(3, init_forces=True)
+    nH, ne, eps, enb = (t.cpu().numpy() for t in md.exchange_inputs())
+    E = md.energy_fx.cpu().numpy().reshape(-1, 4) * FX_E
+    ti = d.t["target_idx"].cpu().numpy().reshape(-1, 4)
+    ctx.check()
+    ctx.close()
+    W = E[:, :3].sum(1)
+    lam = np.asarray(lams)[ti[:, synth.DIM_H]]
+    assert np.allclose(enb, W, rtol=0, atol=1e-9 * np.abs(W).max())
+    assert np.allclose(eps, lam * W + E[:, 3], rtol=0, atol=1e-9 * np.abs(W).max())
+    cfg, st, arr, keep = oracle.make_md(b, seed=3, eps_mode=1)
+    _, _, ep_o = oracle.replica_counts(cfg, b["site_state"], ti, E)
+    assert np.allclose(eps, ep_o, rtol=0, atol=1e-9 * np.abs(W).max())
+
+
 def test_replica_grid_md_with_exchanges_matches_oracle():
     """A 2 x 2 x 2 (E, T, pH) grid, 2 instances, MC every 5 steps and
     exchanges every 10: targets and states follow the oracle exactly."""
