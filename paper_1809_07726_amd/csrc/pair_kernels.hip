@@ -777,17 +777,39 @@ __device__ __forceinline__ float box_gap2(float4 alo, float4 ahi, float4 blo, fl
 
 constexpr int PACK_BATCH = 4;       // tiles whose atoms are loaded together
 
+// Outputs of one radius: rc^2, the blocks' atom counts, the J slots, and (items
+// pass) the run list, its count and the packed tiles' headers.
+struct PackOut {
+    float rc2;
+    int32_t* blk_count;
+    int32_t* pk_j;
+    int2* items;
+    int32_t* count;
+    int32_t* pk_hdr;
+};
+
+// NK = 2 packs the lists of both radii (descreening and energy passes on the
+// same blocking) in one scan: tiles tested against the larger radius, atoms
+// against each.
+template <int NK>
 __global__ __launch_bounds__(256) void k_pack_atoms(
     const int4* __restrict__ win, int n_win, int ni,
     const int32_t* __restrict__ atom_off, const int32_t* __restrict__ tile_base,
-    const float4* __restrict__ box, const float* __restrict__ xyz, int ntot, float rc2,
-    int32_t* __restrict__ blk_count, int32_t* __restrict__ pk_j)
+    const float4* __restrict__ box, const float* __restrict__ xyz, int ntot, PackOut o0, PackOut o1)
 {
-    __shared__ unsigned long long s_mask[MAXW][PACK_WINDOW];
+    __shared__ unsigned long long s_mask[NK][MAXW][PACK_WINDOW];
     __shared__ int s_tile[MAXW][PACK_WINDOW];
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int wi = blockIdx.x * (blockDim.x >> 6) + wv;
     if (wi >= n_win) return;
+    const PackOut* out[2] = {&o0, &o1};
+    float rc2[NK];
+    float rt2 = 0.0f;
+#pragma unroll
+    for (int v = 0; v < NK; ++v) {
+        rc2[v] = out[v]->rc2;
+        rt2 = fmaxf(rt2, rc2[v]);
+    }
     // {block, A << 16 | first tile, the block's first packed tile, replica}
     const int4 wd = win[wi];
     const int rep = wd.w, A = (int)((unsigned)wd.y >> 16), c0 = wd.y & 0xFFFF;
@@ -808,10 +830,12 @@ __global__ __launch_bounds__(256) void k_pack_atoms(
         const int t = c0 + 64 * q + lane;
         bool near = false;
         if (64 * q + lane < PACK_WINDOW && t < T)
-            near = box_gap2(lo, hi, box[2 * (tb + t)], box[2 * (tb + t) + 1]) < rc2;
+            near = box_gap2(lo, hi, box[2 * (tb + t)], box[2 * (tb + t) + 1]) < rt2;
         nmq[q] = __ballot(near);
     }
-    int nn = 0, total = 0;
+    int nn = 0, total[NK];
+#pragma unroll
+    for (int v = 0; v < NK; ++v) total[v] = 0;
     int q = 0;
     unsigned long long nm = nmq[0];
     auto next_tile = [&]() -> int {                // next near tile of the window, or -1
@@ -841,71 +865,87 @@ __global__ __launch_bounds__(256) void k_pack_atoms(
             const float dx = fmaxf(0.0f, fmaxf(lo.x - x[k], x[k] - hi.x));
             const float dy = fmaxf(0.0f, fmaxf(lo.y - y[k], y[k] - hi.y));
             const float dz = fmaxf(0.0f, fmaxf(lo.z - z[k], z[k] - hi.z));
-            const bool keep = bt[k] * 64 + lane < n && dx * dx + dy * dy + dz * dz < rc2;
-            const unsigned long long am = __ballot(keep);
-            if (am) {
+            const float d2 = dx * dx + dy * dy + dz * dz;
+            const bool in = bt[k] * 64 + lane < n;
+            unsigned long long am[NK];
+            unsigned long long anym = 0;
+#pragma unroll
+            for (int v = 0; v < NK; ++v) {
+                am[v] = __ballot(in && d2 < rc2[v]);
+                anym |= am[v];
+            }
+            if (anym) {
                 if (lane == 0) {
-                    s_mask[wv][nn] = am;
+#pragma unroll
+                    for (int v = 0; v < NK; ++v) s_mask[v][wv][nn] = am[v];
                     s_tile[wv][nn] = bt[k];
                 }
                 ++nn;
-                total += __popcll(am);
+#pragma unroll
+                for (int v = 0; v < NK; ++v) total[v] += __popcll(am[v]);
             }
         }
     }
-    if (total == 0) return;
-    int off = 0;
-    if (lane == 0) off = atomicAdd(&blk_count[wd.x], total);
-    off = __shfl(off, 0, 64);
     wave_lds_fence();
     const unsigned long long below = (1ull << lane) - 1ull;
-    int32_t* dst = pk_j + (int64_t)wd.z * 64 + off;
-    for (int k = 0; k < nn; ++k) {
-        const unsigned long long am = s_mask[wv][k];
-        if ((am >> lane) & 1ull) dst[__popcll(am & below)] = s_tile[wv][k] * 64 + lane;
-        dst += __popcll(am);
+#pragma unroll
+    for (int v = 0; v < NK; ++v) {
+        if (total[v] == 0) continue;
+        int off = 0;
+        if (lane == 0) off = atomicAdd(&out[v]->blk_count[wd.x], total[v]);
+        off = __shfl(off, 0, 64);
+        int32_t* dst = out[v]->pk_j + (int64_t)wd.z * 64 + off;
+        for (int k = 0; k < nn; ++k) {
+            const unsigned long long am = s_mask[v][wv][k];
+            if ((am >> lane) & 1ull) dst[__popcll(am & below)] = s_tile[wv][k] * 64 + lane;
+            dst += __popcll(am);
+        }
     }
 }
 
+template <int NK>
 __global__ __launch_bounds__(64) void k_pack_items(
-    const int2* __restrict__ iblk, const int32_t* __restrict__ blk_p0, int n_iblk,
-    int32_t* __restrict__ blk_count, int2* __restrict__ items, int32_t* __restrict__ count,
-    int32_t* __restrict__ pk_hdr)
+    const int2* __restrict__ iblk, const int32_t* __restrict__ blk_p0, int n_iblk, PackOut o0, PackOut o1)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    int cnt = 0;
-    if (w < n_iblk) {
-        cnt = blk_count[w];
-        blk_count[w] = 0;
-    }
-    const int nt = (cnt + 63) >> 6;
-    int pre = nt;                                  // inclusive prefix over the wavefront
-    for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(pre, o, 64);
-        if (lane >= o) pre += v;
-    }
-    const int total = __shfl(pre, 63, 64);
-    if (total == 0) return;
-    int base = 0;
-    if (lane == 63) base = atomicAdd(count, total);
-    base = __shfl(base, 63, 64);
+    const PackOut* out[2] = {&o0, &o1};
     int2 ib = make_int2(0, 0);
     int p0 = 0;
-    if (nt > 0) {
+    if (w < n_iblk) {
         ib = iblk[w];
         p0 = blk_p0[w];
     }
-    // the wavefront writes block L's items together, block by block
-    for (int L = 0; L < 64; ++L) {
-        const int ntL = __shfl(nt, L, 64);
-        if (ntL == 0) continue;
-        const int slot0 = base + __shfl(pre, L, 64) - ntL;
-        const int cntL = __shfl(cnt, L, 64), repL = __shfl(ib.x, L, 64), AL = __shfl(ib.y, L, 64);
-        const int p0L = __shfl(p0, L, 64);
-        for (int p = lane; p < ntL; p += 64) {
-            items[slot0 + p] = make_int2(repL | (ITEM_PACKED << 30), p0L + p);
-            pk_hdr[p0L + p] = (AL << 7) | min(64, cntL - 64 * p);
+#pragma unroll
+    for (int v = 0; v < NK; ++v) {
+        const PackOut& o = *out[v];
+        int cnt = 0;
+        if (w < n_iblk) {
+            cnt = o.blk_count[w];
+            o.blk_count[w] = 0;
+        }
+        const int nt = (cnt + 63) >> 6;
+        int pre = nt;                              // inclusive prefix over the wavefront
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(pre, d, 64);
+            if (lane >= d) pre += t;
+        }
+        const int total = __shfl(pre, 63, 64);
+        if (total == 0) continue;
+        int base = 0;
+        if (lane == 63) base = atomicAdd(o.count, total);
+        base = __shfl(base, 63, 64);
+        // the wavefront writes block L's items together, block by block
+        for (int L = 0; L < 64; ++L) {
+            const int ntL = __shfl(nt, L, 64);
+            if (ntL == 0) continue;
+            const int slot0 = base + __shfl(pre, L, 64) - ntL;
+            const int cntL = __shfl(cnt, L, 64), repL = __shfl(ib.x, L, 64), AL = __shfl(ib.y, L, 64);
+            const int p0L = __shfl(p0, L, 64);
+            for (int p = lane; p < ntL; p += 64) {
+                o.items[slot0 + p] = make_int2(repL | (ITEM_PACKED << 30), p0L + p);
+                o.pk_hdr[p0L + p] = (AL << 7) | min(64, cntL - 64 * p);
+            }
         }
     }
 }
@@ -967,21 +1007,30 @@ hipError_t launch_pack(const gbr_ctx* c, const float* xyz, hipStream_t s) {
     // the tile boxes' FP32 bounds are exact (min / max of the stored
     // coordinates); the margin covers the rounding of the kernels' own r^2
     const double rc[2] = {c->prm.rgbmax * (1.0 + 1e-5) + 1e-4, c->prm.cut * (1.0 + 1e-5) + 1e-4};
-    bool done[4][2] = {};
-    const int use[3] = {c->ni_born, c->ni_energy, c->ni_chain};
-    const int kind[3] = {0, 1, 0};
-    for (int k = 0; k < 3; ++k) {
-        const int idx = use[k] == 1 ? 0 : use[k] == 2 ? 1 : use[k] == 4 ? 2 : 3;
-        if (done[idx][kind[k]]) continue;
-        done[idx][kind[k]] = true;
-        const PairList& L = c->lists[idx];
-        if (L.n_iblk == 0) continue;
-        const int v = kind[k];
-        hipLaunchKernelGGL(k_pack_atoms, dim3((L.n_win + 3) / 4), dim3(256), 0, s, L.win, L.n_win,
-                           L.ni, c->atom_off, c->tile_base, c->tile_box, xyz, c->n_atoms,
-                           (float)(rc[v] * rc[v]), L.blk_count[v], L.pk_j[v]);
-        hipLaunchKernelGGL(k_pack_items, dim3((L.n_iblk + 63) / 64), dim3(64), 0, s, L.iblk, L.blk_p0,
-                           L.n_iblk, L.blk_count[v], L.run[v], L.n_run[v], L.pk_hdr[v]);
+    auto pack_out = [&](const PairList& L, int v) {
+        return PackOut{(float)(rc[v] * rc[v]), L.blk_count[v], L.pk_j[v], L.run[v], L.n_run[v], L.pk_hdr[v]};
+    };
+    auto idx_of = [](int ni) { return ni == 1 ? 0 : ni == 2 ? 1 : ni == 4 ? 2 : 3; };
+    const int ib = idx_of(c->ni_born), ic = idx_of(c->ni_chain), ie = idx_of(c->ni_energy);
+    // lists in use: {list, radius}; a list used with both radii is packed in one scan
+    bool need[4][2] = {};
+    need[ib][0] = need[ic][0] = true;
+    need[ie][1] = true;
+    for (int k = 0; k < 4; ++k) {
+        const PairList& L = c->lists[k];
+        if (L.n_iblk == 0 || !(need[k][0] || need[k][1])) continue;
+        const dim3 ga((L.n_win + 3) / 4), gi((L.n_iblk + 63) / 64);
+        if (need[k][0] && need[k][1]) {
+            const PackOut o0 = pack_out(L, 0), o1 = pack_out(L, 1);
+            hipLaunchKernelGGL(k_pack_atoms<2>, ga, dim3(256), 0, s, L.win, L.n_win, L.ni, c->atom_off,
+                               c->tile_base, c->tile_box, xyz, c->n_atoms, o0, o1);
+            hipLaunchKernelGGL(k_pack_items<2>, gi, dim3(64), 0, s, L.iblk, L.blk_p0, L.n_iblk, o0, o1);
+        } else {
+            const PackOut o = pack_out(L, need[k][0] ? 0 : 1);
+            hipLaunchKernelGGL(k_pack_atoms<1>, ga, dim3(256), 0, s, L.win, L.n_win, L.ni, c->atom_off,
+                               c->tile_base, c->tile_box, xyz, c->n_atoms, o, o);
+            hipLaunchKernelGGL(k_pack_items<1>, gi, dim3(64), 0, s, L.iblk, L.blk_p0, L.n_iblk, o, o);
+        }
     }
     return hipGetLastError();
 }
