@@ -903,49 +903,43 @@ __global__ __launch_bounds__(256) void k_pack_atoms(
     }
 }
 
+// One wavefront per radius and 64 blocks (NK wavefronts per workgroup).
 template <int NK>
-__global__ __launch_bounds__(64) void k_pack_items(
+__global__ __launch_bounds__(64 * NK) void k_pack_items(
     const int2* __restrict__ iblk, const int32_t* __restrict__ blk_p0, int n_iblk, PackOut o0, PackOut o1)
 {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const PackOut* out[2] = {&o0, &o1};
+    const int w = blockIdx.x * 64 + lane;
+    const PackOut& o = (NK == 2 && (threadIdx.x >> 6)) ? o1 : o0;
     int2 ib = make_int2(0, 0);
-    int p0 = 0;
+    int p0 = 0, cnt = 0;
     if (w < n_iblk) {
         ib = iblk[w];
         p0 = blk_p0[w];
+        cnt = o.blk_count[w];
+        o.blk_count[w] = 0;
     }
-#pragma unroll
-    for (int v = 0; v < NK; ++v) {
-        const PackOut& o = *out[v];
-        int cnt = 0;
-        if (w < n_iblk) {
-            cnt = o.blk_count[w];
-            o.blk_count[w] = 0;
-        }
-        const int nt = (cnt + 63) >> 6;
-        int pre = nt;                              // inclusive prefix over the wavefront
-        for (int d = 1; d < 64; d <<= 1) {
-            const int t = __shfl_up(pre, d, 64);
-            if (lane >= d) pre += t;
-        }
-        const int total = __shfl(pre, 63, 64);
-        if (total == 0) continue;
-        int base = 0;
-        if (lane == 63) base = atomicAdd(o.count, total);
-        base = __shfl(base, 63, 64);
-        // the wavefront writes block L's items together, block by block
-        for (int L = 0; L < 64; ++L) {
-            const int ntL = __shfl(nt, L, 64);
-            if (ntL == 0) continue;
-            const int slot0 = base + __shfl(pre, L, 64) - ntL;
-            const int cntL = __shfl(cnt, L, 64), repL = __shfl(ib.x, L, 64), AL = __shfl(ib.y, L, 64);
-            const int p0L = __shfl(p0, L, 64);
-            for (int p = lane; p < ntL; p += 64) {
-                o.items[slot0 + p] = make_int2(repL | (ITEM_PACKED << 30), p0L + p);
-                o.pk_hdr[p0L + p] = (AL << 7) | min(64, cntL - 64 * p);
-            }
+    const int nt = (cnt + 63) >> 6;
+    int pre = nt;                                  // inclusive prefix over the wavefront
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(pre, d, 64);
+        if (lane >= d) pre += t;
+    }
+    const int total = __shfl(pre, 63, 64);
+    if (total == 0) return;
+    int base = 0;
+    if (lane == 63) base = atomicAdd(o.count, total);
+    base = __shfl(base, 63, 64);
+    // the wavefront writes block L's items together, block by block
+    for (int L = 0; L < 64; ++L) {
+        const int ntL = __shfl(nt, L, 64);
+        if (ntL == 0) continue;
+        const int slot0 = base + __shfl(pre, L, 64) - ntL;
+        const int cntL = __shfl(cnt, L, 64), repL = __shfl(ib.x, L, 64), AL = __shfl(ib.y, L, 64);
+        const int p0L = __shfl(p0, L, 64);
+        for (int p = lane; p < ntL; p += 64) {
+            o.items[slot0 + p] = make_int2(repL | (ITEM_PACKED << 30), p0L + p);
+            o.pk_hdr[p0L + p] = (AL << 7) | min(64, cntL - 64 * p);
         }
     }
 }
@@ -1024,7 +1018,7 @@ hipError_t launch_pack(const gbr_ctx* c, const float* xyz, hipStream_t s) {
             const PackOut o0 = pack_out(L, 0), o1 = pack_out(L, 1);
             hipLaunchKernelGGL(k_pack_atoms<2>, ga, dim3(256), 0, s, L.win, L.n_win, L.ni, c->atom_off,
                                c->tile_base, c->tile_box, xyz, c->n_atoms, o0, o1);
-            hipLaunchKernelGGL(k_pack_items<2>, gi, dim3(64), 0, s, L.iblk, L.blk_p0, L.n_iblk, o0, o1);
+            hipLaunchKernelGGL(k_pack_items<2>, gi, dim3(128), 0, s, L.iblk, L.blk_p0, L.n_iblk, o0, o1);
         } else {
             const PackOut o = pack_out(L, need[k][0] ? 0 : 1);
             hipLaunchKernelGGL(k_pack_atoms<1>, ga, dim3(256), 0, s, L.win, L.n_win, L.ni, c->atom_off,
