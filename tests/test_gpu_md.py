@@ -137,6 +137,23 @@ def test_graph_replay_with_hamiltonian_exchanges_is_bitwise_equal_to_eager():
     assert not np.array_equal(eager[-1]["target_idx"][:, synth.DIM_H], b["target_idx"][:, synth.DIM_H])
 
 
+def test_graph_replay_with_packed_cutoff_lists_is_bitwise_equal_to_eager():
+    """Captured step graphs with salt and both cutoffs (the packing kernels and
+    their counter resets inside the graphs, replayed many times, MC every 5
+    steps and exchanges every 10) give the same bits as eager launches."""
+    import paper_1809_07726_amd._capi as A
+    from gpu_common import clear_cutoffs
+    b = with_oracle_gref(synth.make_config(1, n_atoms=700, n_rep=4))
+    b["mc_every"], b["ex_every"] = 5, 10
+    cut, rgb = clear_cutoffs(b, 8.0, 10.0)
+    P = A.obc2(kappa=0.1, cut=cut, rgbmax=rgb)
+    eager = _gpu_md(b, 13, [12, 18], params=P)
+    graph = _gpu_md(b, 13, [12, 18], graph=True, params=P)
+    for e, g in zip(eager, graph):
+        for k in ("xyz", "v", "q", "site_state", "target_idx", "grid_rep", "F_fx"):
+            assert np.array_equal(e[k], g[k]), k
+
+
 def test_gpu_hamiltonian_exchange_samples_the_pair_boltzmann_weights():
     """32 frozen two-replica systems on a 2-level Hamiltonian grid (scales 1.0
     and 0.8), exchange attempts every step on the GPU: each pair holds the
