@@ -201,13 +201,30 @@ def test_ragged_uneven_replicas_with_packed_cutoff_lists(ni):
     _check(b, gpu_eval(b, True, True, blocking=(ni, ni, ni), params=P), _oracle_batch(b, gb=G), grads=True)
 
 
-def test_titration_delta_e_with_salt_and_cutoff_matches_oracle():
+@pytest.mark.parametrize("n_atoms,n_rep", [(None, 3), (5000, 2)])
+def test_titration_delta_e_with_salt_and_cutoff_matches_oracle(n_atoms, n_rep):
+    """Salt and the pair cutoff in the titration sums, with 1,024-atom
+    replicas (one chunk) and 5,000-atom replicas (three chunks)."""
     import paper_1809_07726_amd._capi as A
     import torch
     from paper_1809_07726_amd.gb import Context
     from gpu_common import to_dev
-    b = synth.make_config(1, n_rep=3, per_replica_jitter=True)
-    cut, rgb = clear_cutoffs(b, 9.0, 11.0)
+    b = synth.make_config(1, n_atoms=n_atoms, n_rep=n_rep, per_replica_jitter=True)
+    if n_atoms is None:
+        cut, rgb = clear_cutoffs(b, 9.0, 11.0)
+    else:
+        # many pairs: only the site atoms' distances decide the titration sums,
+        # and the Born radii are left without a cutoff
+        off = b["atom_off"]
+        r = []
+        for s_ in range(b["n_sites"]):
+            rr = int(np.searchsorted(off, b["site_atoms"][b["site_off"][s_]], side="right") - 1)
+            xs = b["xyz"][b["site_atoms"][b["site_off"][s_]:b["site_off"][s_ + 1]]].astype(np.float64)
+            xa = b["xyz"][off[rr]:off[rr + 1]].astype(np.float64)
+            r.append(np.sqrt(((xs[:, None] - xa[None]) ** 2).sum(-1)).ravel())
+        r = np.concatenate(r)
+        cut = next(c for c in 9.0 + 0.013 * np.arange(200) if np.abs(r - c).min() > 5e-5)
+        rgb = 0.0
     P = A.obc2(kappa=0.2, cut=cut, rgbmax=rgb)
     G = oracle.obc2(kappa=0.2, cut=cut, rgbmax=rgb)
     d = to_dev(b)
