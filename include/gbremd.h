@@ -162,7 +162,8 @@ typedef struct {
 /* Create a context for one batch layout on the current HIP device.
  * atom_off_host: HOST array [n_rep+1], atom_off[0] = 0, non-decreasing, every
  * replica with at least 1 atom; 1 <= n_rep < 2^26.  Allocates the workspace (a few int64/float per
- * atom plus the pair work lists; with both cutoffs set also the packed lists,
+ * atom, 4 KiB per replica for the energy pass's partial sums, the pair work
+ * lists; with both cutoffs set also the packed lists,
  * up to 2 x 256 bytes per later tile of every I block and blocking, which the
  * pair passes rebuild from the positions at every evaluation).  Errors:
  * GBR_E_INVAL, GBR_E_NODEVICE, GBR_E_NOMEM, GBR_E_HIP. */

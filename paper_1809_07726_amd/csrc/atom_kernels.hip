@@ -57,8 +57,8 @@ __global__ __launch_bounds__(512) void k_coef(
     const float* __restrict__ q, const float* __restrict__ rho, const float* __restrict__ R,
     const float* __restrict__ dRdpsi, const int64_t* __restrict__ dEdR_fx, double ketau,
     double keout, double kappa, double offset, double* __restrict__ dEdR, float* __restrict__ cc,
-    int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint64_t* __restrict__ step,
-    uint32_t* __restrict__ err)
+    int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, int64_t* __restrict__ e_stripe,
+    uint64_t* __restrict__ step, uint32_t* __restrict__ err)
 {
     const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
     const int lane = threadIdx.x & 63;
@@ -91,6 +91,19 @@ __global__ __launch_bounds__(512) void k_coef(
         v[0] = to_fixed(wave_sum_d(eself), FX_ENERGY, err);
     }
     if (group_runs_by_replica<1>(rep, v)) atomic_add_fx(&energy_fx[4 * rep], v[0]);
+    // the replica's first tile also folds the energy pass's stripes into its
+    // three energy slots and clears them for the next evaluation
+    if (t < n_tiles && tiles[t].y == 0) {
+        long long e[3] = {0, 0, 0};
+        if (lane < E_STRIPES) {
+            int64_t* d = e_stripe + ((size_t)rep * E_STRIPES + lane) * E_STRIPE_LEN;
+            for (int k = 0; k < 3; ++k) { e[k] = d[k]; d[k] = 0; }
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int off = E_STRIPES / 2; off > 0; off >>= 1) e[k] += __shfl_xor(e[k], off, GBR_WAVE);
+        if (lane == 0)
+            for (int k = 0; k < 3; ++k) atomic_add_fx(&energy_fx[4 * rep + k], e[k]);
+    }
 }
 
 // per-atom part of dE/drho_i: dE/dR_i [R^2 (1/rho~^2 - tanh/rho^2) + dR/dpsi * psi/rho~]
@@ -183,7 +196,7 @@ hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const
     hipLaunchKernelGGL(k_coef, dim3((c->n_tiles + 7) / 8), dim3(512), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, q, rho, R, dRdpsi, c->dEdR_fx, k.ke_d * k.tau_d,
                        c->prm.k_e / c->prm.eps_out, c->prm.kappa, c->prm.offset,
-                       c->dEdR, c->chain_c, energy_fx, dEdq_fx, step, c->err);
+                       c->dEdR, c->chain_c, energy_fx, dEdq_fx, c->e_stripe, step, c->err);
     return hipGetLastError();
 }
 

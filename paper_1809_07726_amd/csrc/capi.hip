@@ -145,7 +145,7 @@ int md_forces(gbr_ctx* c, const MDArgs& a, bool with_mc, bool advance, hipStream
     {
         Timed t(c, GBR_K_ENERGY_PAIR, s, true);
         e = launch_energy_pair(c, a.st.xyz, a.st.q, a.st.R, a.pr.sigma, a.pr.eps, a.st.force_fx,
-                               a.st.energy_fx, nullptr, s, t.ev);
+                               nullptr, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "energy pair");
     {
@@ -369,10 +369,13 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     if ((rc = dev_alloc(&c->ex_enb, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->ex_fscale, n_rep))) return done(rc);
     if ((rc = dev_alloc(&c->mc_acc_fx, n_rep))) return done(rc);
+    const size_t n_stripe = (size_t)n_rep * E_STRIPES * E_STRIPE_LEN;
+    if ((rc = dev_alloc(&c->e_stripe, n_stripe))) return done(rc);
     if ((rc = dev_alloc(&c->step, 2))) return done(rc);
     if ((rc = dev_alloc(&c->err, 1))) return done(rc);
     hipError_t e = hipMemset(c->err, 0, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(c->mc_acc_fx, 0, sizeof(int64_t) * n_rep);
+    if (e == hipSuccess) e = hipMemset(c->e_stripe, 0, sizeof(int64_t) * n_stripe);
     if (e == hipSuccess) e = hipMemset(c->step, 0, 2 * sizeof(uint64_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return done(hip_fail(e, "context init"));
@@ -406,7 +409,7 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     (void)hipFree(c->psi_fx); (void)hipFree(c->dEdR_fx); (void)hipFree(c->dEdR); (void)hipFree(c->chain_c);
     (void)hipFree(c->ke_fx); (void)hipFree(c->ex_nH); (void)hipFree(c->ex_ne); (void)hipFree(c->ex_eps);
     (void)hipFree(c->ex_vscale); (void)hipFree(c->ex_enb); (void)hipFree(c->ex_fscale);
-    (void)hipFree(c->mc_acc_fx);
+    (void)hipFree(c->mc_acc_fx); (void)hipFree(c->e_stripe);
     (void)hipFree(c->step); (void)hipFree(c->err);
     delete c;
     if (have_prev && prev != c_dev) (void)hipSetDevice(prev);
@@ -529,7 +532,7 @@ int gb_energy_forces(gbr_ctx* c, const float* xyz, const float* q, const float* 
     if (e != hipSuccess) return hip_fail(e, "zero");
     {
         Timed t(c, GBR_K_ENERGY_PAIR, s, true);
-        e = launch_energy_pair(c, xyz, q, R, sigma, eps, force_fx, energy_fx, gq ? dEdq_fx : nullptr, s, t.ev);
+        e = launch_energy_pair(c, xyz, q, R, sigma, eps, force_fx, gq ? dEdq_fx : nullptr, s, t.ev);
     }
     if (e != hipSuccess) return hip_fail(e, "energy pair");
     {

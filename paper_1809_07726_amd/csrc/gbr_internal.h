@@ -51,6 +51,13 @@ struct Timer {
 
 }  // namespace gbr
 
+// The energy pass adds each wavefront's energy sums into one of E_STRIPES
+// cache lines of the replica rather than into its energy_fx slots: with one
+// large replica, thousands of wavefronts end at about the same time, and adds
+// to one address are served one after another.
+constexpr int E_STRIPES = 32;
+constexpr int E_STRIPE_LEN = 16;     // int64 per stripe: one 128-byte line
+
 struct gbr_ctx {
     int device = 0;
     int n_cu = 256;
@@ -81,6 +88,10 @@ struct gbr_ctx {
     float* ex_vscale = nullptr;
     double* ex_fscale = nullptr;     // [n_rep] force factor after Hamiltonian swaps
     int64_t* mc_acc_fx = nullptr;    // [n_rep] titration attempt dE (2^32), zero between attempts
+    // [n_rep][E_STRIPES][E_STRIPE_LEN] energy-pass sums (E_GB, E_C, E_LJ at 2^32),
+    // zero between evaluations: the energy pass adds into them, k_coef (always
+    // the next launch) folds them into energy_fx and clears them
+    int64_t* e_stripe = nullptr;
     uint64_t* step = nullptr;        // [2] current step index (second word unused)
     uint32_t* err = nullptr;         // device error word
     gbr::Timer timer;
@@ -108,7 +119,7 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
                             const float* screen, hipStream_t s, LaunchEvents ev = {});
 hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q,
                               const float* R, const float* sigma, const float* eps,
-                              int64_t* force_fx, int64_t* energy_fx, int64_t* dEdq_fx,
+                              int64_t* force_fx, int64_t* dEdq_fx,
                               hipStream_t s, LaunchEvents ev = {});
 hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rho,
                              const float* screen, int64_t* force_fx, int64_t* dEdrho_fx,

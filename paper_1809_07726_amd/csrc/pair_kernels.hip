@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     const float* __restrict__ xyz, const float* __restrict__ q, const float* __restrict__ Rb,
     const float* __restrict__ sigma, const float* __restrict__ eps, float sq_ke_in, float taup, PairExt ext,
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdR_fx,
-    int64_t* __restrict__ energy_fx, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
+    int64_t* __restrict__ e_stripe, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
     constexpr int NSL = NI == 2 ? 2 : 1;
     __shared__ float4 lds[MAXW][NSL][2][64];
@@ -372,15 +372,17 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     const float wq = -0.25f * taup;
     if (n_dev) n_items = n_dev[0];                // a packed list: its device count
     // energy sums of the wavefront's current replica (valid in lane 63); one
-    // set of atomics per replica change rather than per item, so that the
-    // items of one large replica do not all meet at its three energy slots
+    // set of atomics per replica change rather than per item, into the stripe
+    // of the replica that this wavefront's index selects
     int e_rep = -1;
     long long e_sum[3] = {0, 0, 0};
+    const int e_str = logical_wave() & (E_STRIPES - 1);
     auto flush_e = [&]() {
         if (e_rep >= 0 && lane == 63) {
-            atomic_add_fx(&energy_fx[4 * e_rep + 0], e_sum[0]);
-            atomic_add_fx(&energy_fx[4 * e_rep + 1], e_sum[1]);
-            atomic_add_fx(&energy_fx[4 * e_rep + 2], e_sum[2]);
+            int64_t* d = e_stripe + ((size_t)e_rep * E_STRIPES + e_str) * E_STRIPE_LEN;
+            atomic_add_fx(&d[0], e_sum[0]);
+            atomic_add_fx(&d[1], e_sum[1]);
+            atomic_add_fx(&d[2], e_sum[2]);
         }
         e_sum[0] = e_sum[1] = e_sum[2] = 0;
     };
@@ -1054,7 +1056,7 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
 
 hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q,
                               const float* R, const float* sigma, const float* eps,
-                              int64_t* force_fx, int64_t* energy_fx, int64_t* dEdq_fx,
+                              int64_t* force_fx, int64_t* dEdq_fx,
                               hipStream_t s, LaunchEvents ev)
 {
     const PairList& L = list_for(c, c->ni_energy);
@@ -1067,7 +1069,7 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     const PairExt pe = make_pair_ext(c, L, 1);
 #define GBR_EN(NI, GQ, EX) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ, EX>), grid, block, 0, s, ev.start, \
         ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, pe, \
-        force_fx, c->dEdR_fx, energy_fx, dEdq_fx, c->err)
+        force_fx, c->dEdR_fx, c->e_stripe, dEdq_fx, c->err)
 #define GBR_EN2(NI, GQ) if (uses_ext(c)) GBR_EN(NI, GQ, true); else GBR_EN(NI, GQ, false)
     const bool gq = dEdq_fx != nullptr;
     switch (L.ni) {
