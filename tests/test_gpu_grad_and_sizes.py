@@ -194,3 +194,35 @@ def test_full_size_100k_salt_cutoff_system_in_the_tuned_launch_sampled():
                                       b["eps"][sel], G)
         Fo = -gs[int(np.searchsorted(sel, i))]
         assert np.linalg.norm(g["F"][i] - Fo) <= 1e-5 * max(np.linalg.norm(Fo), F_rms), (i, g["F"][i], Fo)
+
+
+def test_repeated_evaluations_on_one_context_match_a_fresh_context():
+    """The energy pass adds its sums into per-replica stripes that the next
+    kernel folds into the energies and clears: three evaluations in a row on
+    one context give the results of a fresh context.  The 192 x 1,024 batch
+    (all-pairs lists) matches bit for bit; one 20,000-atom replica with packed
+    lists, whose grouping of J atoms into items follows the atomic append
+    order, matches to FP32 rounding (a stale stripe would double an energy)."""
+    import paper_1809_07726_amd._capi as A
+    from paper_1809_07726_amd.gb import Context
+    b5 = synth.make_config(5, n_atoms=20000)
+    b5["xyz"] = b5["x0"].copy()
+    cases = [(b5, A.obc2(kappa=0.1, cut=12.1, rgbmax=15.1)), (synth.make_config(2), None)]
+    for b, P in cases:
+        ref = gpu_eval(b, params=P)
+        ctx = Context(b["atom_off"], P)
+        t = to_dev(b).t
+        for k in range(3):
+            R, dR, psi = ctx.born_radii(t["xyz"], t["rho"], t["screen"])
+            f, e, _, _ = ctx.energy_forces(t["xyz"], t["q"], t["rho"], t["screen"], t["sigma"], t["eps"],
+                                           R, dR, psi)
+            ctx.check()
+            e, f = e.cpu().numpy(), f.cpu().numpy()
+            if P is None:
+                assert np.array_equal(e, ref["E_fx"]), (b["n_rep"], k)
+                assert np.array_equal(f, ref["F_fx"]), (b["n_rep"], k)
+            else:
+                ev, rv = e.reshape(-1, 4)[:, :3] * 2.0 ** -32, ref["E_fx"].reshape(-1, 4)[:, :3] * 2.0 ** -32
+                assert np.all(np.abs(ev - rv) <= 1e-6 * np.abs(rv).sum()), (k, ev, rv)
+                assert rms_rel(f.astype(np.float64), ref["F_fx"].astype(np.float64)) < 1e-6, k
+        ctx.close()
