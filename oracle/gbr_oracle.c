@@ -31,6 +31,16 @@
  * Everything is O(N^2) double loops in the order of the definitions; no
  * tiling, no fixed point, no fast math.  Parallel loops (OpenMP) are over
  * independent output rows only, each row summed serially in index order.
+ *
+ * Parity unpinned (definitional, checked by eye against the published model):
+ * three choices of the GB model that no closed form, limit or invariant
+ * separates from a close variant -- the signs of the OBC-II polynomial
+ * (alpha psi - beta psi^2 + gamma psi^3), the 4 in Still's exp(-r^2 / (4 Ri
+ * Rj)), and the Lorentz-Berthelot combination (arithmetic sigma, geometric
+ * epsilon) of the Lennard-Jones pair.  Every other part is pinned by the
+ * tests: closed forms, quadrature, limits (the R -> rho rho~ / offset
+ * saturation among them), invariants, finite differences, enumerations and
+ * sampled distributions (eq. 5's exchange energy under titration among them).
  */
 #include <math.h>
 #include <stdint.h>

@@ -60,10 +60,9 @@ def with_oracle_gref(batch, gb=None):
 
 
 # ------------------------------------------------ coupled-site model system
-def coupled_sites_system(seed=41, pH_vals=(6.5,), E_vals=(-0.2,), T_vals=(300.0,), n_inst=1):
-    """The atoms of one pH site and one redox site (taken from a 64-atom
-    lattice system) as a frozen system: dt = 0, attempts every step.  With G_ref
-    from the isolated sites (oracle), replicas on an E x pH grid."""
+def coupled_sites_sysd(seed=41):
+    """The atoms of one pH site and one redox site, taken from a 64-atom
+    lattice system, as a system dict (sites renumbered from 0)."""
     src = synth.make_config(0, n_atoms=64, seed=seed)
     ms = src["max_states"]
     idx = np.concatenate([src["site_atoms"][src["site_off"][s]:src["site_off"][s + 1]] for s in (0, 1)])
@@ -78,6 +77,13 @@ def coupled_sites_system(seed=41, pH_vals=(6.5,), E_vals=(-0.2,), T_vals=(300.0,
                               "nH": [0, 1] if t == 0 else [0, 0], "ne": [0, 0] if t == 0 else [0, 1],
                               "ref": src["ref_value"][s]})
         pos += c - a
+    return sysd
+
+
+def coupled_sites_system(seed=41, pH_vals=(6.5,), E_vals=(-0.2,), T_vals=(300.0,), n_inst=1):
+    """The coupled-site system as a frozen batch: dt = 0, attempts every step.
+    With G_ref from the isolated sites (oracle), replicas on an E x pH grid."""
+    sysd = coupled_sites_sysd(seed)
     G = len(E_vals) * len(pH_vals) * len(T_vals)
     dims = (synth.DIM_E, synth.DIM_PH) + ((synth.DIM_T,) if len(T_vals) > 1 else ())
     b = synth.assemble([sysd] * n_inst, G, E_vals, pH_vals, tuple(T_vals), dims,

@@ -12,7 +12,8 @@ from scipy.integrate import quad
 from scipy.optimize import brentq
 
 import oracle
-from common import (batch_mean_bound, diprotic_site_batch, oracle_reference_energies, three_state_expected,
+from common import (batch_mean_bound, coupled_sites_sysd, diprotic_site_batch, four_state_energies,
+                    four_state_probs, oracle_reference_energies, three_state_expected,
                     with_oracle_gref)
 from paper_1809_07726_amd import synth
 
@@ -162,6 +163,35 @@ def test_obc_rescale_reduces_to_hct_for_small_psi():
         assert abs(1.0 / R[0] - hct_inv) <= 1.01 * bound + 1e-15
         if bound > 1e-12:          # resolvable above roundoff
             assert abs(1.0 / R[0] - hct_inv) >= 0.9 * bound
+
+
+def test_obc_rescale_saturates_at_rho_rho_tilde_over_offset():
+    """Deeply buried atoms: as psi grows, tanh(alpha psi - beta psi^2 + gamma
+    psi^3) -> 1, so 1/R -> 1/rho~ - 1/rho = offset / (rho rho~): R tends to
+    rho rho~ / offset from below, and every R of any system obeys 0 < R <=
+    rho rho~ / offset.  This fixes the denominator rho (the intrinsic radius,
+    not the offset one) of the tanh term."""
+    rng = np.random.default_rng(5)
+    centre = np.zeros((1, 3))
+    for n_shell, rad in ((12, 2.2), (32, 2.0)):
+        d = rng.normal(size=(n_shell, 3))
+        xyz = np.concatenate([centre, rad * d / np.linalg.norm(d, axis=1, keepdims=True)])
+        rho = np.full(n_shell + 1, 1.9)
+        rho[0] = 1.5
+        scr = np.full(n_shell + 1, 0.9)
+        psi, R, _ = oracle.born(xyz, rho, scr)
+        lim = rho * (rho - 0.09) / 0.09
+        assert np.all(R > 0.0) and np.all(R <= lim * (1 + 1e-12))
+        phi = psi[0] - 0.8 * psi[0] ** 2 + 4.85 * psi[0] ** 3
+        if n_shell == 12:                                  # phi = 4.5: within 0.5% of the limit, below it
+            assert 4.0 < phi < 5.0 and 0.995 * lim[0] < R[0] < lim[0]
+        else:                                              # phi > 20: tanh(phi) = 1 in double precision
+            assert phi > 20.0
+            assert R[0] == pytest.approx(lim[0], rel=1e-12)
+    # a moderately buried atom approaches the limit from below
+    xyz = np.array([[0.0, 0.0, 0.0], [3.0, 0.0, 0.0], [-3.0, 0.0, 0.0], [0.0, 3.0, 0.0]])
+    psi, R, _ = oracle.born(xyz, np.full(4, 1.5), np.full(4, 0.8))
+    assert R[0] < 1.5 * 1.41 / 0.09 and R[0] > 1.41
 
 
 # ---------------------------------- P6: invariances and Newton's third law
@@ -655,6 +685,46 @@ def test_exchange_pairs_only_nearest_neighbours_sharing_other_targets():
             c2 = list(c); c2[dim] += 1
             g2 = (c2[0] * 2 + c2[1]) * 2 + c2[2]
             assert gr[g] == bb["grid_rep"][g2] and gr[g2] == bb["grid_rep"][g]
+
+
+def test_temperature_exchange_under_titration_samples_each_temperatures_ensemble():
+    """Eq. 5 with titrating sites (reading A21).  Two frozen copies of a pH +
+    redox site pair sit on a 300 / 345 K ladder, with a protonation and a
+    redox attempt every step and a temperature attempt every other step.  The
+    attempts of eqs. 1-2 sample, at temperature T, the semi-grand weights
+    exp(-[U - G_ref + F (E - E0_ref) N_e] / kT - ln10 (pH - pKa_ref) N_H).
+    The joint chain (both replicas' states and the temperature assignment)
+    keeps the product of those weights, each at the replica's current
+    temperature, only if the exchange energy is U - sum G_ref + sum F (E -
+    E0_ref) N_e: the pH term is temperature-free and cancels.  Then the
+    replica that holds T_k samples the exact four-state distribution at T_k.
+    A dropped or sign-flipped G_ref or redox term in the exchange energy ties
+    the temperature assignment to the states and breaks that match."""
+    T, pH, E = (300.0, 345.0), 6.9, -0.17
+    b = synth.assemble([coupled_sites_sysd(41)], 2, (E,), (pH,), T, (synth.DIM_T,),
+                       dt=0.0, mc_every=1, ex_every=1)
+    b = with_oracle_gref(b)
+    eps = four_state_energies(b)
+    exact = [four_state_probs(eps, pH, E, t, synth.PKA_REF, synth.E0_REF).reshape(-1) for t in T]
+    assert np.abs(exact[0] - exact[1]).max() > 0.05        # the two temperatures differ
+    cfg, st, arr, keep = oracle.make_md(b, seed=83)
+    oracle.md_run(cfg, st, 0, 1, True)
+    n, blocks = 24000, 24
+    occ = np.zeros((blocks, 2, 4))
+    for k in range(n):
+        oracle.md_run(cfg, st, k + 1, 1, False)
+        ti = arr["target_idx"].reshape(2, 4)[:, synth.DIM_T]
+        ss = arr["site_state"].reshape(2, 2)
+        for r in (0, 1):
+            occ[k * blocks // n, ti[r], 2 * ss[r, 0] + ss[r, 1]] += 1
+    assert arr["ex_att"].sum() == n // 2 + 1              # even attempts pair the two points
+    rate = arr["ex_acc"].sum() / arr["ex_att"].sum()
+    assert 0.1 < rate < 0.99, rate                         # exchanges both happen and get refused
+    p_blocks = occ / (n // blocks)
+    p_hat = p_blocks.mean(0)
+    se = p_blocks.std(0, ddof=1) / math.sqrt(blocks)
+    for t in (0, 1):
+        assert np.all(np.abs(p_hat[t] - exact[t]) <= 4.5 * se[t] + 2e-3), (t, p_hat[t], exact[t], se[t])
 
 
 def test_cutoff_forces_and_radii_are_local():
