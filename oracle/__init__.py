@@ -111,7 +111,7 @@ def _declare(L):
     L.orc_energy.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _P(GBParams), _dp]
     L.orc_elec_energy.argtypes = [C.c_int, _dp, _dp, _dp, _P(GBParams)]
     L.orc_elec_energy.restype = C.c_double
-    for fn in (L.orc_delta_e_plain, L.orc_delta_e_incr):
+    for fn in (L.orc_delta_e_plain, L.orc_delta_e_incr, L.orc_delta_e_abs):
         fn.argtypes = [C.c_int, _dp, _dp, _dp, _P(GBParams), C.c_int, _ip, _dp]
         fn.restype = C.c_double
     L.orc_gradient.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _P(GBParams),
@@ -204,6 +204,15 @@ def delta_e(xyz, q, R, idx, qnew, gb=None, incremental=False) -> float:
     idx = _i32(idx)
     fn = lib().orc_delta_e_incr if incremental else lib().orc_delta_e_plain
     return fn(xyz.size // 3, xyz, _f64(q), _f64(R), C.byref(gb), idx.size, idx, _f64(qnew))
+
+
+def delta_e_abs_scale(xyz, q, R, idx, qnew, gb=None) -> float:
+    """Sum of the absolute values of the incremental form's terms (an error
+    scale for a titration energy change evaluated in lower precision)."""
+    gb = gb or obc2()
+    xyz = _f64(xyz).reshape(-1)
+    idx = _i32(idx)
+    return lib().orc_delta_e_abs(xyz.size // 3, xyz, _f64(q), _f64(R), C.byref(gb), idx.size, idx, _f64(qnew))
 
 
 def gradient(xyz, q, rho, scr, sig, eps, gb=None):

@@ -363,6 +363,29 @@ double orc_delta_e_incr(int n, const double* xyz, const double* q, const double*
     return lin + 0.5 * quad;
 }
 
+/* Error scale of the incremental form (not a result of the method): the sum
+ * of the absolute values of its terms,
+ *   sum_k |delta_k| sum_j |K_kj q_j| + (1/2) sum_{k,l} |delta_k delta_l K_kl|.
+ * An evaluation that rounds each term to relative precision u and adds them
+ * up is off by at most a few u times this sum, however much the terms cancel. */
+double orc_delta_e_abs(int n, const double* xyz, const double* q, const double* R,
+                       const orc_gb* p, int m, const int* idx, const double* qnew)
+{
+    double lin = 0.0, quad = 0.0;
+    for (int k = 0; k < m; ++k) {
+        int a = idx[k];
+        double dk = fabs(qnew[k] - q[a]);
+        double Kq = 0.0;
+        for (int j = 0; j < n; ++j) Kq += fabs(orc_K(n, xyz, R, p, a, j) * q[j]);
+        lin += dk * Kq;
+        for (int l = 0; l < m; ++l) {
+            int b = idx[l];
+            quad += fabs(dk * (qnew[l] - q[b]) * orc_K(n, xyz, R, p, a, b));
+        }
+    }
+    return lin + 0.5 * quad;
+}
+
 /* ============================================================== gradients */
 /* Analytic gradient of E = E_GB + E_C + E_LJ with respect to positions,
  * charges and intrinsic radii, by the chain rule through the Born radii:
