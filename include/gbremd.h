@@ -69,6 +69,8 @@ extern "C" {
 #define GBR_ERR_OVERFLOW   0x2u  /* a fixed-point conversion saturated           */
 #define GBR_ERR_RADIUS     0x4u  /* 1/R_i <= 0 or not finite                     */
 #define GBR_ERR_SITE       0x8u  /* titration candidate out of range             */
+#define GBR_ERR_LAYOUT     0x10u /* gb_born_radii_noalloc: atom_off disagrees with
+                                    n_atoms / max_atoms (replica skipped)       */
 
 /* fixed-point scales: stored integer = round(value * 2^bits) */
 #define GBR_FX_BITS_FORCE   40   /* forces, dE/dR, dE/dq, dE/drho (per atom)     */
@@ -342,6 +344,35 @@ typedef struct {
 int md_step(gbr_ctx* ctx, gbr_md_state* state, const gbr_md_params* params,
             uint64_t seed, uint64_t step0, int32_t n_steps, int32_t flags,
             hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the Born
+ * radii of gb_born_radii without a context.  The descreening sums go to a
+ * static device array of GBR_NOALLOC_MAX_ATOMS 64-bit integers (8 MiB), one
+ * per device, held until the process ends; the call allocates nothing.
+ *   params    GB constants as for gbr_ctx_create (HOST pointer); rgbmax is
+ *             honoured, kappa and cut do not enter the Born radii
+ *   atom_off  DEVICE int32 [n_rep+1], replica r owns atoms atom_off[r] ..
+ *             atom_off[r+1]-1, atom_off[0] = 0, atom_off[n_rep] = n_atoms
+ *   n_atoms   1 .. GBR_NOALLOC_MAX_ATOMS (larger: GBR_E_INVAL, nothing launched)
+ *   max_atoms size of the largest replica (it sizes the launch); a replica
+ *             larger than max_atoms, or atom_off ending elsewhere than
+ *             n_atoms, sets GBR_ERR_LAYOUT in *err and that replica's radii
+ *             are not valid
+ *   xyz, rho, screen, R, dRdpsi, psi as for gb_born_radii (psi may be NULL)
+ *   err       DEVICE uint32, GBR_ERR_* bits are OR-ed into it (the caller
+ *             clears it and reads it after synchronizing the stream)
+ * All pairs of a replica, one i tile against one j tile per wavefront: the
+ * results equal gb_born_radii's within FP32 rounding of the per-tile sums.
+ * Every call on a device uses that device's one array: calls that overlap
+ * on one device (other streams, other threads) race and give wrong radii.
+ * The first call on a device, or gbr_ctx_create on it, looks the array up
+ * (no allocation); make that first call outside stream capture. */
+#define GBR_NOALLOC_MAX_ATOMS (1 << 20)
+int gb_born_radii_noalloc(const gbr_gb_params* params, int32_t n_rep, const int32_t* atom_off,
+                          int32_t n_atoms, int32_t max_atoms, const float* xyz, const float* rho,
+                          const float* screen, float* R, float* dRdpsi, double* psi,
+                          uint32_t* err, hipStream_t stream);
 
 /* ------------------------------------------------------------- utilities */
 

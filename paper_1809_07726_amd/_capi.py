@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgbremd.so")
 
 GBR_OK, GBR_E_INVAL, GBR_E_HIP, GBR_E_NOMEM, GBR_E_NODEVICE, GBR_E_NUMERIC = 0, -1, -2, -3, -4, -5
-ERR_NONFINITE, ERR_OVERFLOW, ERR_RADIUS, ERR_SITE = 1, 2, 4, 8
+ERR_NONFINITE, ERR_OVERFLOW, ERR_RADIUS, ERR_SITE, ERR_LAYOUT = 1, 2, 4, 8, 16
+NOALLOC_MAX_ATOMS = 1 << 20
 FX_BITS_FORCE, FX_BITS_ENERGY = 40, 32
 GRAD_Q, GRAD_RHO, ZERO_OUT = 1, 2, 4
 MD_INIT_FORCES, MD_GRAPH = 1, 2
@@ -28,7 +29,7 @@ KERNEL_KINDS = ("born_pair", "energy_pair", "chain_pair", "per_atom", "titration
 EXPORTED = ("gbr_ctx_create", "gbr_ctx_destroy", "gbr_check", "gbr_last_error", "gbr_ctx_sizes",
             "gbr_set_launch", "gbr_set_blocking", "gbr_set_timing", "gbr_get_timing",
             "gb_born_radii", "gb_energy_forces", "titration_delta_e", "remd_exchange", "md_step",
-            "gbr_fx_to_float", "gbr_energies", "gbr_exchange_inputs")
+            "gbr_fx_to_float", "gbr_energies", "gbr_exchange_inputs", "gb_born_radii_noalloc")
 
 
 class GBParams(C.Structure):
@@ -97,6 +98,7 @@ def _load():
     L.gbr_fx_to_float.argtypes = [_vp, _vp, i32, i32, _vp, i32, _vp, _vp]
     L.gbr_energies.argtypes = [_vp, _vp, _vp, _vp]
     L.gbr_exchange_inputs.argtypes = [_vp, P(MDState), P(MDParams), _vp, _vp, _vp, _vp, _vp]
+    L.gb_born_radii_noalloc.argtypes = [P(GBParams), i32, _vp, i32, i32] + [_vp] * 7 + [_vp]
     for name in EXPORTED:
         if name != "gbr_last_error":
             getattr(L, name).restype = C.c_int

@@ -19,20 +19,12 @@ __global__ void k_zero_i64(int64_t* __restrict__ p, int64_t n) {
 }
 
 // psi_i = rho~_i * (1/2) sum_j h_ij;  1/R = 1/rho~ - tanh(alpha psi - beta psi^2 + gamma psi^3)/rho
-__global__ __launch_bounds__(256) void k_born_finalize(
-    const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
-    const float* __restrict__ rho, const int64_t* __restrict__ psi_fx, double offset,
-    double alpha, double beta, double gamma, float* __restrict__ R, float* __restrict__ dRdpsi,
-    double* __restrict__ psi_out, uint32_t* __restrict__ err)
+__device__ __forceinline__ void born_rescale(int a, const float* __restrict__ rho,
+                                             const int64_t* __restrict__ psi_fx, double offset,
+                                             double alpha, double beta, double gamma,
+                                             float* __restrict__ R, float* __restrict__ dRdpsi,
+                                             double* __restrict__ psi_out, uint32_t* __restrict__ err)
 {
-    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
-    if (t >= n_tiles) return;
-    const int lane = threadIdx.x & 63;
-    const int2 tl = tiles[t];
-    const int a0 = atom_off[tl.x], n = atom_off[tl.x + 1] - a0;
-    const int li = tl.y * 64 + lane;
-    if (li >= n) return;
-    const int a = a0 + li;
     const double rh = rho[a], rt = rh - offset;
     const double ps = rt * 0.5 * from_fixed(psi_fx[a], INV_FX_FORCE);
     const double phi = ps * (alpha + ps * (-beta + ps * gamma));
@@ -46,6 +38,35 @@ __global__ __launch_bounds__(256) void k_born_finalize(
     R[a] = (float)Rv;
     dRdpsi[a] = (float)(Rv * Rv * (1.0 - th * th) * (alpha - 2.0 * beta * ps + 3.0 * gamma * ps * ps) / rh);
     if (psi_out) psi_out[a] = ps;
+}
+
+__global__ __launch_bounds__(256) void k_born_finalize(
+    const int2* __restrict__ tiles, int n_tiles, const int32_t* __restrict__ atom_off,
+    const float* __restrict__ rho, const int64_t* __restrict__ psi_fx, double offset,
+    double alpha, double beta, double gamma, float* __restrict__ R, float* __restrict__ dRdpsi,
+    double* __restrict__ psi_out, uint32_t* __restrict__ err)
+{
+    const int t = blockIdx.x * (blockDim.x >> 6) + wave_in_group();
+    if (t >= n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int2 tl = tiles[t];
+    const int a0 = atom_off[tl.x], n = atom_off[tl.x + 1] - a0;
+    const int li = tl.y * 64 + lane;
+    if (li >= n) return;
+    born_rescale(a0 + li, rho, psi_fx, offset, alpha, beta, gamma, R, dRdpsi, psi_out, err);
+}
+
+// The same over a flat range of atoms (no tile list); thread 0 also checks
+// that the replicas end at n atoms.
+__global__ __launch_bounds__(256) void k_born_finalize_flat(
+    int n, int n_rep, const int32_t* __restrict__ atom_off, const float* __restrict__ rho,
+    const int64_t* __restrict__ psi_fx, double offset, double alpha, double beta, double gamma,
+    float* __restrict__ R, float* __restrict__ dRdpsi, double* __restrict__ psi_out,
+    uint32_t* __restrict__ err)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a == 0 && atom_off[n_rep] != n) raise_error(err, GBR_ERR_LAYOUT);
+    if (a < n) born_rescale(a, rho, psi_fx, offset, alpha, beta, gamma, R, dRdpsi, psi_out, err);
 }
 
 // With kg(R) = k_e g(R) = (k_e tau + (k_e/eps_out)(1 - exp(-kappa R))) / R (tau/R
@@ -186,6 +207,14 @@ hipError_t launch_born_finalize(const gbr_ctx* c, const float* rho, float* R, fl
     hipLaunchKernelGGL(k_born_finalize, dim3(tile_grid(c)), dim3(256), 0, s, c->tiles, c->n_tiles,
                        c->atom_off, rho, c->psi_fx, c->prm.offset, c->prm.alpha, c->prm.beta,
                        c->prm.gamma, R, dRdpsi, psi, c->err);
+    return hipGetLastError();
+}
+
+hipError_t launch_born_finalize_flat(const gbr_gb_params& p, int n_atoms, int n_rep,
+                                     const int32_t* atom_off, const float* rho, const int64_t* psi_fx,
+                                     float* R, float* dRdpsi, double* psi, uint32_t* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_born_finalize_flat, dim3((n_atoms + 255) / 256), dim3(256), 0, s, n_atoms, n_rep,
+                       atom_off, rho, psi_fx, p.offset, p.alpha, p.beta, p.gamma, R, dRdpsi, psi, err);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -79,6 +80,41 @@ struct Timed {
         if (ev.stop && !ext) (void)hipEventRecord(ev.stop, s);
     }
 };
+
+// The static scratch of gb_born_radii_noalloc: 64-bit fixed-point descreening
+// sums of up to GBR_NOALLOC_MAX_ATOMS atoms, one copy per device.  Host code
+// never passes `scratch` itself to a kernel (on the host it names a stand-in):
+// it looks up the device address once per device and uses that.
+static __device__ __align__(256) int64_t scratch[GBR_NOALLOC_MAX_ATOMS];
+
+constexpr int MAX_DEVICES = 64;
+struct NoallocDev {
+    int64_t* scratch = nullptr;   // device address of `scratch` on that device
+    int n_cu = 0;
+};
+std::mutex g_noalloc_mu;
+NoallocDev g_noalloc[MAX_DEVICES];
+
+// Device address of the scratch array on the current device dev (looked up
+// on first use) and its CU count; checks that the device is gfx950.
+int noalloc_device(int dev, NoallocDev* out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(GBR_E_INVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    NoallocDev& d = g_noalloc[dev];
+    if (!d.scratch) {
+        hipDeviceProp_t prop;
+        GBR_HIP(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(GBR_E_NODEVICE, "device %d is %s; this library is built for gfx950", dev,
+                        prop.gcnArchName);
+        void* p = nullptr;
+        GBR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        d.n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        d.scratch = static_cast<int64_t*>(p);
+    }
+    *out = d;
+    return GBR_OK;
+}
 
 int check_ctx(const gbr_ctx* c) {
     if (!c) return fail(GBR_E_INVAL, "null context");
@@ -272,6 +308,10 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
         return fail(GBR_E_NODEVICE, "device %d is %s; this library is built for gfx950", dev,
                     prop.gcnArchName);
 
+    {
+        NoallocDev nd;   // set-up of gb_born_radii_noalloc's scratch on this device
+        if (int rc = noalloc_device(dev, &nd)) return rc;
+    }
     gbr_ctx* c = new gbr_ctx();
     c->device = dev;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -503,6 +543,37 @@ int gb_born_radii(gbr_ctx* c, const float* xyz, const float* rho, const float* s
         e = launch_born_finalize(c, rho, R, dRdpsi, psi, s);
     }
     if (e != hipSuccess) return hip_fail(e, "born finalize");
+    return GBR_OK;
+}
+
+int gb_born_radii_noalloc(const gbr_gb_params* params, int32_t n_rep, const int32_t* atom_off,
+                          int32_t n_atoms, int32_t max_atoms, const float* xyz, const float* rho,
+                          const float* screen, float* R, float* dRdpsi, double* psi, uint32_t* err,
+                          hipStream_t s) {
+    REQ(params); REQ(atom_off); REQ(xyz); REQ(rho); REQ(screen); REQ(R); REQ(dRdpsi); REQ(err);
+    if (n_rep < 1 || n_rep >= gbr::MAX_REPLICAS) return fail(GBR_E_INVAL, "n_rep out of range");
+    if (n_atoms < 1 || n_atoms > GBR_NOALLOC_MAX_ATOMS)
+        return fail(GBR_E_INVAL, "n_atoms = %d: gb_born_radii_noalloc takes 1 .. %d atoms (its static scratch)",
+                    n_atoms, GBR_NOALLOC_MAX_ATOMS);
+    if (max_atoms < 1 || max_atoms > n_atoms)
+        return fail(GBR_E_INVAL, "max_atoms = %d must lie in 1 .. n_atoms", max_atoms);
+    const int T = (max_atoms + 63) / 64;
+    if ((int64_t)n_rep * T * T >= (int64_t)1 << 31)
+        return fail(GBR_E_INVAL, "n_rep x (max_atoms / 64)^2 too large for one launch");
+    const gbr_gb_params& p = *params;
+    if (!(p.offset >= 0) || !(p.alpha == p.alpha && p.beta == p.beta && p.gamma == p.gamma) ||
+        !(p.rgbmax >= 0 && p.rgbmax <= 1e6))
+        return fail(GBR_E_INVAL, "GB parameters out of range");
+    int dev = 0;
+    GBR_HIP(hipGetDevice(&dev));
+    NoallocDev nd;
+    if (int rc = noalloc_device(dev, &nd)) return rc;
+    hipError_t e = launch_zero_i64(nd.scratch, n_atoms, s);
+    if (e == hipSuccess)
+        e = launch_born_pair_gen(p, n_rep, T, atom_off, n_atoms, nd.n_cu, xyz, rho, screen, nd.scratch, err, s);
+    if (e == hipSuccess)
+        e = launch_born_finalize_flat(p, n_atoms, n_rep, atom_off, rho, nd.scratch, R, dRdpsi, psi, err, s);
+    if (e != hipSuccess) return hip_fail(e, "gb_born_radii_noalloc");
     return GBR_OK;
 }
 

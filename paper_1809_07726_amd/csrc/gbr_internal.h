@@ -125,6 +125,13 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
                              const float* screen, int64_t* force_fx, int64_t* dEdrho_fx,
                              hipStream_t s, LaunchEvents ev = {});
 
+// The descreening pass without a context or list (gb_born_radii_noalloc):
+// items generated from the wavefront index over max_tiles tiles per replica,
+// NI = 1, the rgbmax cutoff when set; sums into psi_fx (zeroed by the caller).
+hipError_t launch_born_pair_gen(const gbr_gb_params& p, int n_rep, int max_tiles, const int32_t* atom_off,
+                                int n_atoms, int n_cu, const float* xyz, const float* rho,
+                                const float* screen, int64_t* psi_fx, uint32_t* err, hipStream_t s);
+
 // With both cutoffs: per-tile bounding boxes of xyz, then for every list in
 // use and every I block the atoms after the block that come within rgbmax
 // (for the descreening passes) or cut (for the energy pass) of its box,
@@ -135,6 +142,9 @@ hipError_t launch_pack(const gbr_ctx* c, const float* xyz, hipStream_t s);
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_born_finalize(const gbr_ctx* c, const float* rho, float* R, float* dRdpsi,
                                 double* psi, hipStream_t s);
+hipError_t launch_born_finalize_flat(const gbr_gb_params& p, int n_atoms, int n_rep,
+                                     const int32_t* atom_off, const float* rho, const int64_t* psi_fx,
+                                     float* R, float* dRdpsi, double* psi, uint32_t* err, hipStream_t s);
 hipError_t launch_coef(const gbr_ctx* c, const float* q, const float* rho, const float* R,
                        const float* dRdpsi, int64_t* energy_fx, int64_t* dEdq_fx, uint64_t* step,
                        hipStream_t s);

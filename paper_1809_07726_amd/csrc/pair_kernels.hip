@@ -225,17 +225,42 @@ __device__ __forceinline__ bool both_far(float r, float mi, float mj, float sxi,
     return r >= fmaxf(mi + mj, fmaxf(sxi, sxj));
 }
 
+// Items generated from the wavefront index instead of read from a list (the
+// context-free descreening pass, NI = 1): it = (rep T + A) T + B over the
+// replicas and the 64-atom tiles of the largest replica (T of them); A == B is
+// tile A's triangle item, B > A the block item (A, B); an index with B < A or
+// a tile past the end of its replica carries no item.  A replica that does
+// not fit T tiles, or that reaches past ntot atoms, sets GBR_ERR_LAYOUT and
+// is skipped.
+__device__ __forceinline__ bool gen_item(int it, int T, const int32_t* __restrict__ atom_off, int ntot,
+                                         uint32_t* err, int2& wi) {
+    const int TT = T * T;
+    const int rep = it / TT, rem = it - rep * TT;
+    const int A = rem / T, B = rem - A * T;
+    if (B < A) return false;
+    const int a0 = atom_off[rep], a1 = atom_off[rep + 1];
+    if (a0 < 0 || a1 < a0 || a1 > ntot || a1 - a0 > 64 * T) {
+        if (A == 0 && B == 0) raise_error(err, GBR_ERR_LAYOUT);
+        return false;
+    }
+    if (B * 64 >= a1 - a0) return false;
+    wi = make_int2(rep | ((A == B ? ITEM_TRIANGLE : ITEM_BLOCK) << 30), (A << 16) | B);
+    return true;
+}
+
 // ------------------------------------------------------------- descreening
 // Distant spheres: h = (x^3/r) G(x^2) with x = s/r, i.e. h = s^3 r^-4 G(s^2 r^-2).
 // j tile in LDS: {x, y, z, s}, {rt, m, sx, s^3}
-template <int NI, bool EXT>
+// GEN: items from gen_item (gen_T tiles per replica at most) instead of a list.
+template <int NI, bool EXT, bool GEN = false>
 __global__ __launch_bounds__(256) void k_born_pair(
     const int2* __restrict__ items, int n_items, const int32_t* __restrict__ n_dev,
     const int32_t* __restrict__ atom_off, int ntot,
     const float* __restrict__ xyz, const float* __restrict__ rho,
     const float* __restrict__ screen, float offset, PairExt ext, int64_t* __restrict__ psi_fx,
-    uint32_t* __restrict__ err)
+    uint32_t* __restrict__ err, int gen_T = 0)
 {
+    static_assert(!GEN || NI == 1, "generated items are one-tile items");
     constexpr int NSL = NI == 2 ? 2 : 1;           // j tiles per wavefront
     __shared__ float4 lds[MAXW][NSL][2][64];
     const int lane = threadIdx.x & 63, wv = wave_in_group();
@@ -243,7 +268,13 @@ __global__ __launch_bounds__(256) void k_born_pair(
     const float ixmax = 1.0f / HCT_FAR_XMAX;
     if (n_dev) n_items = n_dev[0];                // a packed list: its device count
     for (int it = logical_wave(); it < n_items; it += stride) {
-        const ItemGeom g = item_geom<NI, EXT>(items[it], atom_off, ext);
+        int2 wi;
+        if constexpr (GEN) {
+            if (!gen_item(it, gen_T, atom_off, ntot, err, wi)) continue;
+        } else {
+            wi = items[it];
+        }
+        const ItemGeom g = item_geom<NI, EXT>(wi, atom_off, ext);
         float xi[NI], yi[NI], zi[NI], rti[NI], si[NI], s2i[NI], s3i[NI], mi[NI], sxi[NI], acc[NI];
         int li[NI];
 #pragma unroll
@@ -1043,7 +1074,7 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
     const PairExt pe = make_pair_ext(c, L, 0);
     const bool ext = uses_ext(c);
 #define GBR_BORN(NI, EX) hipExtLaunchKernelGGL((k_born_pair<NI, EX>), grid, block, 0, s, ev.start, ev.stop, 0, \
-        items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, off, pe, c->psi_fx, c->err)
+        items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, off, pe, c->psi_fx, c->err, 0)
     switch (L.ni) {
         case 1: if (ext) GBR_BORN(1, true); else GBR_BORN(1, false); break;
         case 2: if (ext) GBR_BORN(2, true); else GBR_BORN(2, false); break;
@@ -1051,6 +1082,28 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
         default: if (ext) GBR_BORN(8, true); else GBR_BORN(8, false); break;
     }
 #undef GBR_BORN
+    return hipGetLastError();
+}
+
+hipError_t launch_born_pair_gen(const gbr_gb_params& p, int n_rep, int max_tiles, const int32_t* atom_off,
+                                int n_atoms, int n_cu, const float* xyz, const float* rho,
+                                const float* screen, int64_t* psi_fx, uint32_t* err, hipStream_t s)
+{
+    const int64_t n_items = (int64_t)n_rep * max_tiles * max_tiles;   // checked < 2^31 by the caller
+    const int64_t want = (n_items + 3) / 4;
+    int g = (int)std::min<int64_t>(want, (int64_t)n_cu * 8);
+    if (g >= 8) g = (g + 7) & ~7;               // multiple of 8 for the XCD remapping
+    PairExt pe{};
+    pe.rgb2 = p.rgbmax > 0 ? (float)(p.rgbmax * p.rgbmax) : FLT_MAX;
+    const float off = (float)p.offset;
+    if (p.rgbmax > 0)
+        hipLaunchKernelGGL((k_born_pair<1, true, true>), dim3(g), dim3(256), 0, s, (const int2*)nullptr,
+                           (int)n_items, (const int32_t*)nullptr, atom_off, n_atoms, xyz, rho, screen, off, pe,
+                           psi_fx, err, max_tiles);
+    else
+        hipLaunchKernelGGL((k_born_pair<1, false, true>), dim3(g), dim3(256), 0, s, (const int2*)nullptr,
+                           (int)n_items, (const int32_t*)nullptr, atom_off, n_atoms, xyz, rho, screen, off, pe,
+                           psi_fx, err, max_tiles);
     return hipGetLastError();
 }
 
