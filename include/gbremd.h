@@ -192,7 +192,9 @@ const char* gbr_last_error(void);
 int gbr_ctx_sizes(const gbr_ctx* ctx, int32_t* n_atoms, int32_t* n_rep, int64_t* n_pairs);
 
 /* Pair-kernel launch shape: waves per workgroup (1, 2 or 4) and workgroups per
- * compute unit for the persistent grid (1..32).  Defaults 4 and 8. */
+ * compute unit for the persistent grid (1..32).  Defaults 4 and 8.  The shape
+ * changes no result; captured md_step graphs are dropped and recaptured with
+ * the new shape on next use. */
 int gbr_set_launch(gbr_ctx* ctx, int32_t waves_per_group, int32_t groups_per_cu);
 
 /* Register blocking of the three pair passes: i atoms held per lane (1, 2, 4

@@ -1,4 +1,5 @@
-"""Builds libgbremd.so (all HIP sources, gfx950) in the package directory.
+"""Builds libgbremd.so (all HIP sources, gfx950) in the package directory, and
+the issue-rate microbenchmark's libissue_rate.so next to its source.
 
 Usage: python -m paper_1809_07726_amd.build   (or build() from Python)."""
 import concurrent.futures as cf
@@ -40,6 +41,8 @@ def build(verbose: bool = True) -> str:
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
+    from paper_1809_07726_amd.microbench import issue_rate   # the VALU issue-rate microbenchmark
+    issue_rate.build()
     return LIB
 
 

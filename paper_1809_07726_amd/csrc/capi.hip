@@ -471,6 +471,8 @@ int gbr_set_launch(gbr_ctx* c, int32_t waves_per_group, int32_t groups_per_cu) {
     if (groups_per_cu < 1 || groups_per_cu > 32) return fail(GBR_E_INVAL, "groups_per_cu 1..32");
     c->shape.waves_per_group = waves_per_group;
     c->shape.groups_per_cu = groups_per_cu;
+    // captured step graphs hold the old grids
+    for (auto& g : c->graph) if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     return GBR_OK;
 }
 

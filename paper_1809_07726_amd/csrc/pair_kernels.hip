@@ -262,7 +262,8 @@ __global__ __launch_bounds__(256) void k_born_pair(
 {
     static_assert(!GEN || NI == 1, "generated items are one-tile items");
     constexpr int NSL = NI == 2 ? 2 : 1;           // j tiles per wavefront
-    __shared__ float4 lds[MAXW][NSL][2][64];
+    extern __shared__ float4 lds_dyn[];          // j tiles: [waves in the group][NSL][2][64]
+    auto lds = reinterpret_cast<float4 (*)[NSL][2][64]>(lds_dyn);
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
@@ -395,7 +396,8 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     int64_t* __restrict__ e_stripe, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
     constexpr int NSL = NI == 2 ? 2 : 1;
-    __shared__ float4 lds[MAXW][NSL][2][64];
+    extern __shared__ float4 lds_dyn[];          // j tiles: [waves in the group][NSL][2][64]
+    auto lds = reinterpret_cast<float4 (*)[NSL][2][64]>(lds_dyn);
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float lc = 0.60056120439322491f;       // sqrt(log2(e) / 4)
@@ -605,7 +607,8 @@ __global__ __launch_bounds__(256) void k_chain_pair(
     int64_t* __restrict__ force_fx, int64_t* __restrict__ dEdrho_fx, uint32_t* __restrict__ err)
 {
     constexpr int NSL = NI == 2 ? 2 : 1;
-    __shared__ float4 lds[MAXW][NSL][3][64];
+    extern __shared__ float4 lds_dyn[];          // j tiles: [waves in the group][NSL][3][64]
+    auto lds = reinterpret_cast<float4 (*)[NSL][3][64]>(lds_dyn);
     const int lane = threadIdx.x & 63, wv = wave_in_group();
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float ixmax = 1.0f / HCT_FAR_XMAX;
@@ -986,6 +989,13 @@ int grid_for(const gbr_ctx* c, int n_items) {
     return (g + 7) & ~7;   // multiple of 8 for the XCD remapping
 }
 
+// Dynamic LDS of a pair kernel: the j tiles of the group's own wavefronts
+// (comps float4 per atom, two tiles per wavefront at NI = 2), so that groups
+// of fewer wavefronts take less LDS and more of them fit a CU.
+size_t pair_lds(int waves, int ni, int comps) {
+    return (size_t)waves * (ni == 2 ? 2 : 1) * comps * 64 * sizeof(float4);
+}
+
 // Nothing to launch: the timing events still get recorded (an empty interval).
 hipError_t no_launch(hipStream_t s, const LaunchEvents& ev) {
     if (ev.start) (void)hipEventRecord(ev.start, s);
@@ -1073,7 +1083,8 @@ hipError_t launch_born_pair(const gbr_ctx* c, const float* xyz, const float* rho
     const float off = (float)c->prm.offset;
     const PairExt pe = make_pair_ext(c, L, 0);
     const bool ext = uses_ext(c);
-#define GBR_BORN(NI, EX) hipExtLaunchKernelGGL((k_born_pair<NI, EX>), grid, block, 0, s, ev.start, ev.stop, 0, \
+#define GBR_BORN(NI, EX) hipExtLaunchKernelGGL((k_born_pair<NI, EX>), grid, block, \
+        pair_lds(c->shape.waves_per_group, NI, 2), s, ev.start, ev.stop, 0, \
         items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, off, pe, c->psi_fx, c->err, 0)
     switch (L.ni) {
         case 1: if (ext) GBR_BORN(1, true); else GBR_BORN(1, false); break;
@@ -1097,11 +1108,11 @@ hipError_t launch_born_pair_gen(const gbr_gb_params& p, int n_rep, int max_tiles
     pe.rgb2 = p.rgbmax > 0 ? (float)(p.rgbmax * p.rgbmax) : FLT_MAX;
     const float off = (float)p.offset;
     if (p.rgbmax > 0)
-        hipLaunchKernelGGL((k_born_pair<1, true, true>), dim3(g), dim3(256), 0, s, (const int2*)nullptr,
+        hipLaunchKernelGGL((k_born_pair<1, true, true>), dim3(g), dim3(256), pair_lds(4, 1, 2), s, (const int2*)nullptr,
                            (int)n_items, (const int32_t*)nullptr, atom_off, n_atoms, xyz, rho, screen, off, pe,
                            psi_fx, err, max_tiles);
     else
-        hipLaunchKernelGGL((k_born_pair<1, false, true>), dim3(g), dim3(256), 0, s, (const int2*)nullptr,
+        hipLaunchKernelGGL((k_born_pair<1, false, true>), dim3(g), dim3(256), pair_lds(4, 1, 2), s, (const int2*)nullptr,
                            (int)n_items, (const int32_t*)nullptr, atom_off, n_atoms, xyz, rho, screen, off, pe,
                            psi_fx, err, max_tiles);
     return hipGetLastError();
@@ -1120,7 +1131,8 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     const float sq = (float)sqrt(c->prm.k_e / c->prm.eps_in);
     const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
     const PairExt pe = make_pair_ext(c, L, 1);
-#define GBR_EN(NI, GQ, EX) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ, EX>), grid, block, 0, s, ev.start, \
+#define GBR_EN(NI, GQ, EX) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ, EX>), grid, block, \
+        pair_lds(c->shape.waves_per_group, NI, 2), s, ev.start, \
         ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, pe, \
         force_fx, c->dEdR_fx, c->e_stripe, dEdq_fx, c->err)
 #define GBR_EN2(NI, GQ) if (uses_ext(c)) GBR_EN(NI, GQ, true); else GBR_EN(NI, GQ, false)
@@ -1147,7 +1159,8 @@ hipError_t launch_chain_pair(const gbr_ctx* c, const float* xyz, const float* rh
     const int32_t* n_dev = c->packed ? L.n_run[0] : nullptr;
     const float off = (float)c->prm.offset;
     const PairExt pe = make_pair_ext(c, L, 0);
-#define GBR_CH(NI, RH, EX) hipExtLaunchKernelGGL((k_chain_pair<NI, RH, EX>), grid, block, 0, s, ev.start, \
+#define GBR_CH(NI, RH, EX) hipExtLaunchKernelGGL((k_chain_pair<NI, RH, EX>), grid, block, \
+        pair_lds(c->shape.waves_per_group, NI, 3), s, ev.start, \
         ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, rho, screen, c->chain_c, off, pe, \
         force_fx, dEdrho_fx, c->err)
 #define GBR_CH2(NI, RH) if (uses_ext(c)) GBR_CH(NI, RH, true); else GBR_CH(NI, RH, false)

@@ -1,7 +1,7 @@
-"""Device code of the library compiled to gfx950 assembly (hipcc -S, no GPU
-needed): no scalar-memory writes of any kind, no packed FP32 arithmetic (the
-build disables it), no register spills in the force-only pair kernels, and no
-FP64 arithmetic in the pair kernels."""
+"""Device code of the library and of the issue-rate microbenchmark compiled
+to gfx950 assembly (hipcc -S, no GPU needed): no scalar-memory writes of any
+kind, no packed FP32 arithmetic (the build disables it), no register spills
+in the force-only pair kernels, and no FP64 arithmetic in the pair kernels."""
 import os
 import re
 import subprocess
@@ -10,7 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1809_07726_amd", "csrc")
-SOURCES = ["pair_kernels.hip", "atom_kernels.hip", "md_kernels.hip", "capi.hip"]
+SOURCES = ["pair_kernels.hip", "atom_kernels.hip", "md_kernels.hip", "capi.hip", "../microbench/issue_rate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SCALAR_WRITE = re.compile(r"^\s+s_(store|buffer_store|atomic|buffer_atomic|scratch_store|dcache_wb|dcache_discard)\w*\b",
@@ -26,7 +26,7 @@ def asm(tmp_path_factory):
     d = tmp_path_factory.mktemp("isa")
     out = {}
     for src in SOURCES:
-        dst = d / (src + ".s")
+        dst = d / (os.path.basename(src) + ".s")
         subprocess.check_call([HIPCC, *FLAGS, "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", str(dst)],
                               stderr=subprocess.DEVNULL)
         out[src] = dst.read_text()
