@@ -107,6 +107,18 @@ def pair_counts(b, cut):
     return out
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(b, n_rep_sample, gpu_ref=None, ext=None, rep_pairs=None, min_s=10.0, budget_s=20.0):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
     full E+F gradient evaluations of successive replicas (cycling through the
@@ -140,6 +152,7 @@ def cpu_baseline(b, n_rep_sample, gpu_ref=None, ext=None, rep_pairs=None, min_s=
     sizes = np.diff(off)
     size_txt = (f"{sizes[0]} atoms" if np.all(sizes == sizes[0]) else f"{sizes.min()}..{sizes.max()} atoms")
     out = {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
            "sample": f"{done} replica evaluations ({done / b['n_rep']:.2f} passes over the "
                      f"{b['n_rep']} replicas of {size_txt}): one FP64 Born-radii + energy + "
                      f"analytic-gradient evaluation each ({dt:.1f} s)"}

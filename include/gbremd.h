@@ -215,7 +215,10 @@ int gbr_get_timing(gbr_ctx* ctx, double* ms_out, int64_t* count_out);
 
 /* --------------------------------------------------------------- the path */
 
-/* Effective Born radii (HCT descreening with OBC rescaling):
+/* Effective Born radii of the OBC generalized Born model (igb=2), the solvent
+ * model of MD and of every titration attempt (Calculation details, "Implicit
+ * Solvent Calculations"); the paper names the model, the formulas are the
+ * published HCT descreening integral with the OBC rescaling:
  *   psi_i   = rho~_i * (1/2) sum_{j != i} h(r_ij; rho~_i, S_j rho~_j),  rho~ = rho - offset
  *   1/R_i   = 1/rho~_i - tanh(alpha psi_i - beta psi_i^2 + gamma psi_i^3) / rho_i
  *   dRdpsi_i = R_i^2 (1 - tanh^2) (alpha - 2 beta psi_i + 3 gamma psi_i^2) / rho_i
@@ -228,7 +231,9 @@ int gb_born_radii(gbr_ctx* ctx, const float* xyz, const float* rho, const float*
                   float* R, float* dRdpsi, double* psi, hipStream_t stream);
 
 /* GB + Coulomb + Lennard-Jones energy and forces of every replica at given
- * Born radii (from gb_born_radii on the same xyz/rho/screen):
+ * Born radii (from gb_born_radii on the same xyz/rho/screen): the implicit-
+ * solvent potential of the MD (Calculation details, "Implicit Solvent
+ * Calculations", igb=2; all pairs, no exclusions, Lorentz-Berthelot LJ):
  *   E_GB = -k_e tau [ sum_{i<j} q_i q_j / f_ij + (1/2) sum_i q_i^2 / R_i ],
  *          tau = 1/eps_in - 1/eps_out, f_ij = sqrt(r^2 + R_i R_j exp(-r^2 / (4 R_i R_j)))
  *   E_C  = (k_e / eps_in) sum_{i<j} q_i q_j / r_ij
@@ -251,6 +256,10 @@ int gb_energy_forces(gbr_ctx* ctx, const float* xyz, const float* q, const float
                      int64_t* dEdq_fx, int64_t* dEdrho_fx, hipStream_t stream);
 
 /* Electrostatic energy change of titration candidates at fixed Born radii:
+ * the energy term of the Metropolis test of a protonation or redox attempt
+ * (Theory, "Constant pH and Redox Potential Molecular Dynamics": a change of
+ * protonation or redox state is a change of the site's charges, accepted
+ * with the weights whose stationary fractions are eqs. 1 and 2):
  *   dE = sum_{k in S} d_k (K q)_k + (1/2) sum_{k,l in S} d_k d_l K_kl,
  *   K_ij = k_e (1/(eps_in r_ij) - tau / f_ij) (i != j), K_ii = -k_e tau / R_i,
  * where S is the candidate site's atoms and d = (charges of the new state) - q.
@@ -320,7 +329,10 @@ typedef struct {
 } gbr_md_params;
 
 /* n_steps BAOAB Langevin steps of every replica at its current temperature
- * target (step indices step0 .. step0+n_steps-1).  Step n: B (half kick with
+ * target (step indices step0 .. step0+n_steps-1): C(pH,E)MD with replica
+ * exchange (Theory: MD halted for a protonation then a redox attempt;
+ * exchanges along one dimension at a time, eqs. 3-5; Calculation details:
+ * Langevin dynamics, here with the BAOAB splitting).  Step n: B (half kick with
  * the forces in state), A (half drift), O (exact Ornstein-Uhlenbeck at
  * T[iT], Philox normals), A; if (n+1) % mc_every == 0: Born radii at the new
  * positions, one protonation attempt then one redox attempt per replica
