@@ -39,12 +39,8 @@
  *   - Units: A, e, kcal/mol, amu, ps, K, V.
  *   - Accumulated outputs are 64-bit fixed point (value * 2^bits, round to
  *     nearest even), so results are bit-identical run to run for a given
- *     binary and input.  Exception: with both cutoffs set (packed lists) and
- *     a replica of more than 64 tiles (4,096 atoms), the packing appends the
- *     J atoms of each 64-tile window with an atomic, so the grouping of J
- *     atoms into work items, and with it the FP32 rounding of the per-item
- *     sums, can change from run to run (differences at FP32 rounding level;
- *     the fixed-point sums themselves stay order-independent).
+ *     binary, register blocking and input, also with both cutoffs set (the
+ *     packed cutoff lists place every atom by the coordinates alone).
  */
 #ifndef GBREMD_H
 #define GBREMD_H

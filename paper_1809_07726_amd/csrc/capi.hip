@@ -362,12 +362,14 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
         std::vector<gbr::PairItem> intra, iblocks;
         std::vector<int32_t> p0;
         std::vector<gbr::PackWindow> wins;
+        std::vector<int32_t> blk_win;
         static_assert(sizeof(gbr::PackWindow) == sizeof(int4), "window layout");
         for (int k = 0; k < 4; ++k) {
             gbr::PairList& L = c->lists[k];
             gbr::build_pair_items(c->h_atom_off.data(), n_rep, nis[k], items);
             int64_t cap = 0;
-            gbr::build_packed_parts(c->h_atom_off.data(), n_rep, nis[k], items, intra, iblocks, p0, wins, cap);
+            gbr::build_packed_parts(c->h_atom_off.data(), n_rep, nis[k], items, intra, iblocks, p0, wins, blk_win,
+                                    cap);
             if ((int64_t)intra.size() + cap > 0x7FFFFFFF || cap * 64 > 0x7FFFFFFF)
                 return done(fail(GBR_E_INVAL, "work list too long"));
             L.n_intra = (int32_t)intra.size();
@@ -381,6 +383,8 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
             if (!p0.empty() && (rc = upload(L.blk_p0, p0.data(), sizeof(int32_t) * p0.size()))) return done(rc);
             if ((rc = dev_alloc(&L.win, wins.size()))) return done(rc);
             if (!wins.empty() && (rc = upload(L.win, wins.data(), sizeof(int4) * wins.size()))) return done(rc);
+            if ((rc = dev_alloc(&L.blk_win, blk_win.size()))) return done(rc);
+            if ((rc = upload(L.blk_win, blk_win.data(), sizeof(int32_t) * blk_win.size()))) return done(rc);
             for (int v = 0; v < 2; ++v) {
                 if ((rc = dev_alloc(&L.blk_count[v], iblocks.size()))) return done(rc);
                 if (hipMemset(L.blk_count[v], 0, sizeof(int32_t) * std::max<size_t>(iblocks.size(), 1)) != hipSuccess)
@@ -437,7 +441,7 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     (void)hipFree(c->atom_off);
     (void)hipFree(c->tiles);
     for (auto& L : c->lists) {
-        (void)hipFree(L.items); (void)hipFree(L.iblk); (void)hipFree(L.blk_p0); (void)hipFree(L.win);
+        (void)hipFree(L.items); (void)hipFree(L.iblk); (void)hipFree(L.blk_p0); (void)hipFree(L.win); (void)hipFree(L.blk_win);
         for (int v = 0; v < 2; ++v) {
             (void)hipFree(L.run[v]); (void)hipFree(L.blk_count[v]); (void)hipFree(L.pk_hdr[v]);
             (void)hipFree(L.pk_j[v]);

@@ -29,6 +29,7 @@ struct PairList {
     int32_t n_iblk = 0;
     int4* win = nullptr;                         // packing windows (pair_list.h PackWindow)
     int32_t n_win = 0;
+    int32_t* blk_win = nullptr;                  // [n_iblk + 1] each block's first window
     int64_t pk_cap = 0;                          // packed tiles at most (tiles after each block)
     int32_t* blk_count[2] = {nullptr, nullptr};  // [n_iblk] atoms packed, zero between evaluations
     int32_t* pk_hdr[2] = {nullptr, nullptr};     // [pk_cap] A << 7 | nj

@@ -793,14 +793,18 @@ __global__ __launch_bounds__(256) void k_tile_boxes(
 // Packing, in two passes.  Every I block (rep, A) with tiles after it owns
 // the packed tiles P0 .. P0 + (T - t1) - 1 (t1: the first tile after the
 // block), as many as it has tiles after it, and their 64 J slots each.
-//  k_pack_atoms: one wavefront per window of up to PACK_WINDOW tiles after a block;
+//  k_pack_atoms: one workgroup per I block, its PACK_WAVES wavefronts scanning
+//    the block's windows of up to PACK_WINDOW tiles (one window each per round):
 //    the tiles whose box comes within rc of the block's box, then their atoms
-//    within rc of it, appended to the block's slots (one atomic per window on
-//    the block's atom count; the windows' atoms land in arbitrary order).
+//    within rc of it, written to the block's slots in window, tile and lane
+//    order (each window after the counts of the windows before it).  Where
+//    every atom lands depends on the coordinates alone, so the packed items
+//    (and the FP32 sums over them) are the same at every evaluation of the
+//    same positions.
 //  k_pack_items: one lane per block; its atoms form ceil(count / 64) packed
 //    items {rep | ITEM_PACKED << 30, P}, pk_hdr[P] = A << 7 | nj, appended to
-//    the list after its intra-block items; the count is cleared for the next
-//    evaluation.
+//    the list after its intra-block items (in an order that changes no
+//    result); the count is cleared for the next evaluation.
 // Every pair the packing drops is farther apart than rc, so the kernels'
 // cutoff would have made its terms exact zeros; the order of the J atoms and
 // of the items changes no result (fixed-point sums).
@@ -827,17 +831,19 @@ struct PackOut {
 // NK = 2 packs the lists of both radii (descreening and energy passes on the
 // same blocking) in one scan: tiles tested against the larger radius, atoms
 // against each.
+constexpr int PACK_WAVES = 8;       // wavefronts of a packing workgroup (windows per round)
+
 template <int NK>
-__global__ __launch_bounds__(256) void k_pack_atoms(
-    const int4* __restrict__ win, int n_win, int ni,
+__global__ __launch_bounds__(64 * PACK_WAVES) void k_pack_atoms(
+    const int4* __restrict__ win, const int32_t* __restrict__ blk_win, int n_iblk, int ni,
     const int32_t* __restrict__ atom_off, const int32_t* __restrict__ tile_base,
     const float4* __restrict__ box, const float* __restrict__ xyz, int ntot, PackOut o0, PackOut o1)
 {
-    __shared__ unsigned long long s_mask[NK][MAXW][PACK_WINDOW];
-    __shared__ int s_tile[MAXW][PACK_WINDOW];
-    const int lane = threadIdx.x & 63, wv = wave_in_group();
-    const int wi = blockIdx.x * (blockDim.x >> 6) + wv;
-    if (wi >= n_win) return;
+    __shared__ unsigned long long s_mask[NK][PACK_WAVES][PACK_WINDOW];
+    __shared__ int s_tile[PACK_WAVES][PACK_WINDOW];
+    __shared__ int s_tot[NK][PACK_WAVES];
+    const int lane = threadIdx.x & 63, wv = wave_in_group(), nw = (int)(blockDim.x >> 6);
+    const int bi = blockIdx.x;                         // one workgroup per I block
     const PackOut* out[2] = {&o0, &o1};
     float rc2[NK];
     float rt2 = 0.0f;
@@ -846,9 +852,11 @@ __global__ __launch_bounds__(256) void k_pack_atoms(
         rc2[v] = out[v]->rc2;
         rt2 = fmaxf(rt2, rc2[v]);
     }
-    // {block, A << 16 | first tile, the block's first packed tile, replica}
-    const int4 wd = win[wi];
-    const int rep = wd.w, A = (int)((unsigned)wd.y >> 16), c0 = wd.y & 0xFFFF;
+    const int w0 = blk_win[bi], w1 = blk_win[bi + 1];
+    // {block, A << 16 | first tile, the block's first packed tile, replica}:
+    // block, tile range and replica from the first window
+    const int4 wd0 = win[w0];
+    const int rep = wd0.w, A = (int)((unsigned)wd0.y >> 16);
     const int a0 = atom_off[rep], n = atom_off[rep + 1] - a0;
     const int T = (n + 63) >> 6, tb = tile_base[rep];
     const int t0 = A * ni, t1 = min(T, t0 + ni);
@@ -858,84 +866,109 @@ __global__ __launch_bounds__(256) void k_pack_atoms(
         lo = make_float4(fminf(lo.x, l.x), fminf(lo.y, l.y), fminf(lo.z, l.z), 0.0f);
         hi = make_float4(fmaxf(hi.x, h.x), fmaxf(hi.y, h.y), fmaxf(hi.z, h.z), 0.0f);
     }
-    // the window's tiles, 64 to a ballot word (lane l of word q: tile c0 + 64 q + l)
-    constexpr int NQ = (PACK_WINDOW + 63) / 64;
-    unsigned long long nmq[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int t = c0 + 64 * q + lane;
-        bool near = false;
-        if (64 * q + lane < PACK_WINDOW && t < T)
-            near = box_gap2(lo, hi, box[2 * (tb + t)], box[2 * (tb + t) + 1]) < rt2;
-        nmq[q] = __ballot(near);
-    }
-    int nn = 0, total[NK];
-#pragma unroll
-    for (int v = 0; v < NK; ++v) total[v] = 0;
-    int q = 0;
-    unsigned long long nm = nmq[0];
-    auto next_tile = [&]() -> int {                // next near tile of the window, or -1
-        while (!nm && q + 1 < NQ) nm = nmq[++q];
-        if (!nm) return -1;
-        const int b = c0 + 64 * q + __ffsll((long long)nm) - 1;
-        nm &= nm - 1ull;
-        return b;
-    };
-    for (;;) {
-        int bt[PACK_BATCH];
-        float x[PACK_BATCH], y[PACK_BATCH], z[PACK_BATCH];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < PACK_BATCH; ++k) {
-            bt[k] = next_tile();
-            if (bt[k] >= 0) {
-                any = true;
-                const int jl = min(bt[k] * 64 + lane, n - 1);
-                x[k] = xyz[a0 + jl]; y[k] = xyz[ntot + a0 + jl]; z[k] = xyz[2 * ntot + a0 + jl];
-            }
-        }
-        if (!any) break;
-#pragma unroll
-        for (int k = 0; k < PACK_BATCH; ++k) {
-            if (bt[k] < 0) break;
-            const float dx = fmaxf(0.0f, fmaxf(lo.x - x[k], x[k] - hi.x));
-            const float dy = fmaxf(0.0f, fmaxf(lo.y - y[k], y[k] - hi.y));
-            const float dz = fmaxf(0.0f, fmaxf(lo.z - z[k], z[k] - hi.z));
-            const float d2 = dx * dx + dy * dy + dz * dz;
-            const bool in = bt[k] * 64 + lane < n;
-            unsigned long long am[NK];
-            unsigned long long anym = 0;
-#pragma unroll
-            for (int v = 0; v < NK; ++v) {
-                am[v] = __ballot(in && d2 < rc2[v]);
-                anym |= am[v];
-            }
-            if (anym) {
-                if (lane == 0) {
-#pragma unroll
-                    for (int v = 0; v < NK; ++v) s_mask[v][wv][nn] = am[v];
-                    s_tile[wv][nn] = bt[k];
-                }
-                ++nn;
-#pragma unroll
-                for (int v = 0; v < NK; ++v) total[v] += __popcll(am[v]);
-            }
-        }
-    }
-    wave_lds_fence();
     const unsigned long long below = (1ull << lane) - 1ull;
+    int done[NK];                                      // atoms of this block placed so far, per radius
 #pragma unroll
-    for (int v = 0; v < NK; ++v) {
-        if (total[v] == 0) continue;
-        int off = 0;
-        if (lane == 0) off = atomicAdd(&out[v]->blk_count[wd.x], total[v]);
-        off = __shfl(off, 0, 64);
-        int32_t* dst = out[v]->pk_j + (int64_t)wd.z * 64 + off;
-        for (int k = 0; k < nn; ++k) {
-            const unsigned long long am = s_mask[v][wv][k];
-            if ((am >> lane) & 1ull) dst[__popcll(am & below)] = s_tile[wv][k] * 64 + lane;
-            dst += __popcll(am);
+    for (int v = 0; v < NK; ++v) done[v] = 0;
+    constexpr int NQ = (PACK_WINDOW + 63) / 64;
+    // rounds of nw windows: wavefront w scans window w0 + nw r + w; the
+    // round's counts are met in LDS and each window writes after the windows
+    // before it, so the slots follow window, tile and lane order
+    for (int wr = w0; wr < w1; wr += nw) {
+        const int wi = wr + wv;
+        int nn = 0, total[NK];
+#pragma unroll
+        for (int v = 0; v < NK; ++v) total[v] = 0;
+        if (wi < w1) {
+            const int c0 = win[wi].y & 0xFFFF;
+            // the window's tiles, 64 to a ballot word (lane l of word q: tile c0 + 64 q + l)
+            unsigned long long nmq[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int t = c0 + 64 * q + lane;
+                bool near = false;
+                if (64 * q + lane < PACK_WINDOW && t < T)
+                    near = box_gap2(lo, hi, box[2 * (tb + t)], box[2 * (tb + t) + 1]) < rt2;
+                nmq[q] = __ballot(near);
+            }
+            int q = 0;
+            unsigned long long nm = nmq[0];
+            auto next_tile = [&]() -> int {            // next near tile of the window, or -1
+                while (!nm && q + 1 < NQ) nm = nmq[++q];
+                if (!nm) return -1;
+                const int b = c0 + 64 * q + __ffsll((long long)nm) - 1;
+                nm &= nm - 1ull;
+                return b;
+            };
+            for (;;) {
+                int bt[PACK_BATCH];
+                float x[PACK_BATCH], y[PACK_BATCH], z[PACK_BATCH];
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < PACK_BATCH; ++k) {
+                    bt[k] = next_tile();
+                    if (bt[k] >= 0) {
+                        any = true;
+                        const int jl = min(bt[k] * 64 + lane, n - 1);
+                        x[k] = xyz[a0 + jl]; y[k] = xyz[ntot + a0 + jl]; z[k] = xyz[2 * ntot + a0 + jl];
+                    }
+                }
+                if (!any) break;
+#pragma unroll
+                for (int k = 0; k < PACK_BATCH; ++k) {
+                    if (bt[k] < 0) break;
+                    const float dx = fmaxf(0.0f, fmaxf(lo.x - x[k], x[k] - hi.x));
+                    const float dy = fmaxf(0.0f, fmaxf(lo.y - y[k], y[k] - hi.y));
+                    const float dz = fmaxf(0.0f, fmaxf(lo.z - z[k], z[k] - hi.z));
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = bt[k] * 64 + lane < n;
+                    unsigned long long am[NK];
+                    unsigned long long anym = 0;
+#pragma unroll
+                    for (int v = 0; v < NK; ++v) {
+                        am[v] = __ballot(in && d2 < rc2[v]);
+                        anym |= am[v];
+                    }
+                    if (anym) {
+                        if (lane == 0) {
+#pragma unroll
+                            for (int v = 0; v < NK; ++v) s_mask[v][wv][nn] = am[v];
+                            s_tile[wv][nn] = bt[k];
+                        }
+                        ++nn;
+#pragma unroll
+                        for (int v = 0; v < NK; ++v) total[v] += __popcll(am[v]);
+                    }
+                }
+            }
         }
+        if (lane == 0) {
+#pragma unroll
+            for (int v = 0; v < NK; ++v) s_tot[v][wv] = total[v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NK; ++v) {
+            int before = done[v], all = done[v];
+            for (int u = 0; u < nw; ++u) {
+                if (u < wv) before += s_tot[v][u];
+                all += s_tot[v][u];
+            }
+            if (total[v] > 0) {
+                int32_t* dst = out[v]->pk_j + (int64_t)wd0.z * 64 + before;
+                for (int k = 0; k < nn; ++k) {
+                    const unsigned long long am = s_mask[v][wv][k];
+                    if ((am >> lane) & 1ull) dst[__popcll(am & below)] = s_tile[wv][k] * 64 + lane;
+                    dst += __popcll(am);
+                }
+            }
+            done[v] = all;
+        }
+        __syncthreads();                               // the next round reuses s_mask, s_tile, s_tot
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int v = 0; v < NK; ++v) out[v]->blk_count[bi] = done[v];
     }
 }
 
@@ -1056,15 +1089,15 @@ hipError_t launch_pack(const gbr_ctx* c, const float* xyz, hipStream_t s) {
     for (int k = 0; k < 4; ++k) {
         const PairList& L = c->lists[k];
         if (L.n_iblk == 0 || !(need[k][0] || need[k][1])) continue;
-        const dim3 ga((L.n_win + 3) / 4), gi((L.n_iblk + 63) / 64);
+        const dim3 ga(L.n_iblk), gi((L.n_iblk + 63) / 64);
         if (need[k][0] && need[k][1]) {
             const PackOut o0 = pack_out(L, 0), o1 = pack_out(L, 1);
-            hipLaunchKernelGGL(k_pack_atoms<2>, ga, dim3(256), 0, s, L.win, L.n_win, L.ni, c->atom_off,
+            hipLaunchKernelGGL(k_pack_atoms<2>, ga, dim3(64 * PACK_WAVES), 0, s, L.win, L.blk_win, L.n_iblk, L.ni, c->atom_off,
                                c->tile_base, c->tile_box, xyz, c->n_atoms, o0, o1);
             hipLaunchKernelGGL(k_pack_items<2>, gi, dim3(128), 0, s, L.iblk, L.blk_p0, L.n_iblk, o0, o1);
         } else {
             const PackOut o = pack_out(L, need[k][0] ? 0 : 1);
-            hipLaunchKernelGGL(k_pack_atoms<1>, ga, dim3(256), 0, s, L.win, L.n_win, L.ni, c->atom_off,
+            hipLaunchKernelGGL(k_pack_atoms<1>, ga, dim3(64 * PACK_WAVES), 0, s, L.win, L.blk_win, L.n_iblk, L.ni, c->atom_off,
                                c->tile_base, c->tile_box, xyz, c->n_atoms, o, o);
             hipLaunchKernelGGL(k_pack_items<1>, gi, dim3(64), 0, s, L.iblk, L.blk_p0, L.n_iblk, o, o);
         }

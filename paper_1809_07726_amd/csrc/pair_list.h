@@ -133,7 +133,7 @@ inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vec
 // with tiles after them, each owning as many packed tiles (from p0 on) as it
 // has tiles after it (cap in all); and the windows of up to PACK_WINDOW of
 // those tiles that the packing scans, {block, A << 16 | first tile, block's
-// p0, replica}.
+// p0, replica}, block b's windows being blk_win[b] .. blk_win[b + 1] - 1.
 constexpr int32_t PACK_WINDOW = 64;
 
 struct PackWindow {
@@ -143,11 +143,13 @@ struct PackWindow {
 inline void build_packed_parts(const int32_t* off, int32_t n_rep, int ni,
                                const std::vector<PairItem>& items, std::vector<PairItem>& intra,
                                std::vector<PairItem>& iblocks, std::vector<int32_t>& p0,
-                               std::vector<PackWindow>& windows, int64_t& cap) {
+                               std::vector<PackWindow>& windows, std::vector<int32_t>& blk_win,
+                               int64_t& cap) {
     intra.clear();
     iblocks.clear();
     p0.clear();
     windows.clear();
+    blk_win.assign(1, 0);
     cap = 0;
     for (const PairItem& it : items) {
         const bool block = ((uint32_t)it.x >> 30) == (uint32_t)ITEM_BLOCK;
@@ -164,6 +166,7 @@ inline void build_packed_parts(const int32_t* off, int32_t n_rep, int ni,
             p0.push_back((int32_t)cap);
             for (int32_t c0 = t1; c0 < T; c0 += PACK_WINDOW)
                 windows.push_back(PackWindow{blk, (a << 16) | c0, (int32_t)cap, r});
+            blk_win.push_back((int32_t)windows.size());
             cap += T - t1;
         }
     }

@@ -200,11 +200,11 @@ def test_full_size_100k_salt_cutoff_system_in_the_tuned_launch_sampled():
 
 def test_repeated_evaluations_on_one_context_match_a_fresh_context():
     """The energy pass adds its sums into per-replica stripes that the next
-    kernel folds into the energies and clears: three evaluations in a row on
-    one context give the results of a fresh context.  The 192 x 1,024 batch
-    (all-pairs lists) matches bit for bit; one 20,000-atom replica with packed
-    lists, whose grouping of J atoms into items follows the atomic append
-    order, matches to FP32 rounding (a stale stripe would double an energy)."""
+    kernel folds into the energies and clears, and the packing rebuilds the
+    cutoff lists at every evaluation: three evaluations in a row on one
+    context give the bits of a fresh context, for the 192 x 1,024 batch
+    (all-pairs lists) and for one 20,000-atom replica with packed lists (a
+    stale stripe would double an energy)."""
     import paper_1809_07726_amd._capi as A
     from paper_1809_07726_amd.gb import Context
     b5 = synth.make_config(5, n_atoms=20000)
@@ -220,11 +220,88 @@ def test_repeated_evaluations_on_one_context_match_a_fresh_context():
                                            R, dR, psi)
             ctx.check()
             e, f = e.cpu().numpy(), f.cpu().numpy()
-            if P is None:
-                assert np.array_equal(e, ref["E_fx"]), (b["n_rep"], k)
-                assert np.array_equal(f, ref["F_fx"]), (b["n_rep"], k)
-            else:
-                ev, rv = e.reshape(-1, 4)[:, :3] * 2.0 ** -32, ref["E_fx"].reshape(-1, 4)[:, :3] * 2.0 ** -32
-                assert np.all(np.abs(ev - rv) <= 1e-6 * np.abs(rv).sum()), (k, ev, rv)
-                assert rms_rel(f.astype(np.float64), ref["F_fx"].astype(np.float64)) < 1e-6, k
+            assert np.array_equal(e, ref["E_fx"]), (b["n_rep"], k)
+            assert np.array_equal(f, ref["F_fx"]), (b["n_rep"], k)
         ctx.close()
+
+
+def _jittered_20k():
+    """20,000 atoms in compact 64-atom blocks with their lattice jitter (so
+    pair distances are continuous and each I block's atoms come from up to
+    five windows of the packing)."""
+    return synth.make_config(5, n_atoms=20000)
+
+
+def test_packed_lists_are_bit_reproducible_on_a_jittered_20k_system():
+    """With salt and both cutoffs the packing places every J atom by the
+    coordinates alone: two fresh contexts, in each of two blockings, give
+    identical bits for radii, forces and energies."""
+    import paper_1809_07726_amd._capi as A
+    b = _jittered_20k()
+    P = A.obc2(kappa=0.1, cut=12.0, rgbmax=15.0)
+    for blk in ((1, 1, 1), (2, 2, 2)):
+        print(f"case: jittered 20,000 atoms, blocking {blk}", flush=True)
+        g1 = gpu_eval(b, True, True, blocking=blk, params=P)
+        g2 = gpu_eval(b, True, True, blocking=blk, params=P)
+        for k in ("R", "F_fx", "E_fx", "dEdq", "dEdrho"):
+            assert np.array_equal(g1[k], g2[k]), (blk, k)
+
+
+def test_jittered_20k_system_at_the_requested_cutoffs_matches_oracle():
+    """Off the lattice and at the requested cutoffs (cut 12 A, rgbmax 15 A, no
+    clearing): a pair whose distance lies within FP32 rounding of a cutoff may
+    be counted on one side and not on the other.  FP64 lists the pairs within
+    2e-5 A of either cutoff (about a hundred times the FP32 rounding of r):
+      - Born radii: atoms in no such rgbmax pair within 2e-6 of the oracle; the
+        others between the oracle's radii with rgbmax -+ 2e-5 A;
+      - energies at the GPU's own radii (so that only the pair cutoff is left):
+        within 1e-6 relative plus the summed |GB + C + LJ| pair energies of the
+        pairs near cut (each from the oracle on the two atoms alone);
+      - forces: 1e-5 RMS-relative against the oracle."""
+    import paper_1809_07726_amd._capi as A
+    from scipy.spatial import cKDTree
+    b = _jittered_20k()
+    cut, rgb, kap, dl = 12.0, 15.0, 0.1, 2e-5
+    P = A.obc2(kappa=kap, cut=cut, rgbmax=rgb)
+    G = oracle.obc2(kappa=kap, cut=cut, rgbmax=rgb)
+    print("case: jittered 20,000 atoms, requested cutoffs", flush=True)
+    g = gpu_eval(b, params=P)
+    x = b["xyz"].astype(np.float64)
+    tree = cKDTree(x)
+    def near(rc):
+        pr = tree.query_pairs(rc + dl, output_type="ndarray").astype(np.int64).reshape(-1, 2)
+        r = np.sqrt(((x[pr[:, 0]] - x[pr[:, 1]]) ** 2).sum(1))
+        return pr[np.abs(r - rc) < dl]
+    near_cut, near_rgb = near(cut), near(rgb)
+    print(f"pairs within {dl} A: {len(near_cut)} of cut, {len(near_rgb)} of rgbmax", flush=True)
+    # Born radii
+    _, Ro, _ = oracle.born(x, b["rho"], b["screen"], G)
+    _, Rlo, _ = oracle.born(x, b["rho"], b["screen"], oracle.obc2(kappa=kap, cut=cut, rgbmax=rgb - dl))
+    _, Rhi, _ = oracle.born(x, b["rho"], b["screen"], oracle.obc2(kappa=kap, cut=cut, rgbmax=rgb + dl))
+    edge = np.zeros(len(x), bool)
+    edge[near_rgb.reshape(-1)] = True
+    rel = np.abs(g["R"] / Ro - 1)
+    note("Born radius rel (off the rgbmax edge)", rel[~edge].max())
+    assert rel[~edge].max() < 2e-6
+    lo, hi = np.minimum(Rlo, Rhi), np.maximum(Rlo, Rhi)
+    assert np.all(g["R"][edge] >= lo[edge] * (1 - 2e-6)) and np.all(g["R"][edge] <= hi[edge] * (1 + 2e-6))
+    # energies at the GPU's radii
+    Rg = g["R"].astype(np.float64)
+    Eo = oracle.energy_at_R(x, b["q"], Rg, b["sigma"], b["eps"], G)
+    free = oracle.obc2(kappa=kap)
+    bound = 0.0
+    for i, j in near_cut:
+        two = oracle.energy_at_R(x[[i, j]], b["q"][[i, j]], Rg[[i, j]], b["sigma"][[i, j]], b["eps"][[i, j]], free)
+        one = sum(oracle.energy_at_R(x[[k]], b["q"][[k]], Rg[[k]], b["sigma"][[k]], b["eps"][[k]], free)
+                  for k in (i, j))
+        bound += np.abs(two - one).sum()
+    Eg = g["E"][0]
+    err = abs(Eg[4] - Eo.sum())
+    note("energy err over (1e-6 |E| + near-cut pair terms)", err / (1e-6 * abs(Eo.sum()) + bound))
+    assert err <= 1e-6 * abs(Eo.sum()) + bound, (Eg, Eo, bound)
+    assert abs(Eg[0] - Eo[0]) <= 1e-6 * abs(Eo[0]) + bound
+    # forces
+    _, gx, _, _ = oracle.gradient(x, b["q"], b["rho"], b["screen"], b["sigma"], b["eps"], G)
+    e_rms = rms_rel(g["F"], -gx)
+    note("force rms-rel", e_rms)
+    assert e_rms < 1e-5

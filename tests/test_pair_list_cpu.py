@@ -205,15 +205,17 @@ int main(int argc, char** argv) {
     std::vector<gbr::PairItem> items, intra, blocks;
     std::vector<int32_t> p0;
     std::vector<gbr::PackWindow> wins;
+    std::vector<int32_t> blk_win;
     int64_t cap = 0;
     gbr::build_pair_items(off.data(), (int32_t)off.size() - 1, ni, items);
-    gbr::build_packed_parts(off.data(), (int32_t)off.size() - 1, ni, items, intra, blocks, p0, wins, cap);
+    gbr::build_packed_parts(off.data(), (int32_t)off.size() - 1, ni, items, intra, blocks, p0, wins, blk_win,
+                            cap);
     std::printf("cap %lld\n", (long long)cap);
     for (const auto& it : intra)
         std::printf("I %d %d %d %d %d\n", it.x & 0x3FFFFFF, (int)((unsigned)it.x >> 30), it.y >> 16,
                     it.y & 0xFFFF, (it.x >> 26) & 3);
     for (size_t b = 0; b < blocks.size(); ++b)
-        std::printf("B %d %d %d\n", blocks[b].x, blocks[b].y, p0[b]);
+        std::printf("B %d %d %d %d %d\n", blocks[b].x, blocks[b].y, p0[b], blk_win[b], blk_win[b + 1]);
     for (const auto& w : wins) std::printf("W %d %d %d %d %d\n", w.blk, w.a_c0 & 0xFFFF, w.p0, w.a_c0 >> 16, w.rep);
     return 0;
 }
@@ -242,20 +244,21 @@ def test_packed_lists_cover_every_pair_once(harness, pack_harness, ni):
     out = subprocess.check_output([pack_harness, str(ni)] + [str(s) for s in sizes], text=True).splitlines()
     cap = int(out[0].split()[1])
     intra = np.array([list(map(int, l.split()[1:])) for l in out if l[0] == "I"], np.int64).reshape(-1, 5)
-    blocks = np.array([list(map(int, l.split()[1:])) for l in out if l[0] == "B"], np.int64).reshape(-1, 3)
+    blocks = np.array([list(map(int, l.split()[1:])) for l in out if l[0] == "B"], np.int64).reshape(-1, 5)
     wins = np.array([list(map(int, l.split()[1:])) for l in out if l[0] == "W"], np.int64).reshape(-1, 5)
     full = _items(harness, ni, sizes)
     A_, B_ = full[:, 2], full[:, 3]
     inside = (full[:, 1] != 0) | (B_ < (A_ + 1) * ni)
     assert np.array_equal(intra, full[inside])
     p_next = 0
-    for b, (r, A, p0) in enumerate(blocks):
+    for b, (r, A, p0, wb, we) in enumerate(blocks):
         n = sizes[r]
         T = (n + 63) // 64
         t1 = min(T, (A + 1) * ni)
         assert t1 < T and p0 == p_next
         p_next += T - t1
         w = wins[wins[:, 0] == b]
+        assert np.array_equal(np.flatnonzero(wins[:, 0] == b), np.arange(wb, we))   # the block's window range
         tiles = np.concatenate([np.arange(c0, min(c0 + 64, T)) for c0 in w[:, 1]])
         assert np.array_equal(tiles, np.arange(t1, T)) and np.all(w[:, 2] == p0)
         assert np.all(w[:, 3] == A) and np.all(w[:, 4] == r)
@@ -263,7 +266,7 @@ def test_packed_lists_cover_every_pair_once(harness, pack_harness, ni):
     for r, n in enumerate(sizes):
         its = intra[intra[:, 0] == r]
         P = [_pairs_of_item(n, ni, *it[1:]) for it in its]
-        for (rr, A, p0) in blocks[blocks[:, 0] == r]:
+        for (rr, A, p0, _, _) in blocks[blocks[:, 0] == r]:
             T = (n + 63) // 64
             t1 = min(T, (A + 1) * ni)
             i = np.arange(64 * ni * A, 64 * t1)
