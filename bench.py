@@ -323,6 +323,7 @@ def main():
         pt = autotune(reps[big][0], {"xyz": reps[big][1], "q": reps[big][2], "rho": reps[big][3],
                                      "screen": reps[big][4], "sigma": reps[big][5], "eps": reps[big][6]})
         for pc in pctx.values():
+            pc.set_split(pt["split"])
             pc.set_launch(*pt["shape"])
             pc.set_blocking(*pt["blocking"])
         plain_pass()
@@ -361,7 +362,8 @@ def main():
                    "ex_every": w.ex_every, "graph": bool(args.graph),
                    "accumulation": "int64 fixed point (forces 2^-40, energies 2^-32)",
                    "tuned": {"waves_per_group_x_groups_per_cu": tuned["shape"],
-                             "i_atoms_per_lane_born_energy_chain": tuned["blocking"]}},
+                             "i_atoms_per_lane_born_energy_chain": tuned["blocking"],
+                             "split_den": tuned["split"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_fp64": err64,

@@ -198,6 +198,15 @@ int gbr_set_launch(gbr_ctx* ctx, int32_t waves_per_group, int32_t groups_per_cu)
  * chosen from the largest replica at context creation. */
 int gbr_set_blocking(gbr_ctx* ctx, int32_t ni_born, int32_t ni_energy, int32_t ni_chain);
 
+/* Split level of the pair work lists: the last ceil(nb / split_den) of each
+ * replica's nb block items run as two half items (rotation steps 0..31 and
+ * 32..63), 1 <= split_den <= 1024 (default 16; 1 halves every block item, so
+ * that a small batch has more, shorter items for the chip's wavefront slots).
+ * Rebuilds the lists (synchronizes the device) and drops captured md_step
+ * graphs.  Results are bit-reproducible for one split level, blocking and
+ * input; another split level changes the FP32 rounding of per-item sums. */
+int gbr_set_split(gbr_ctx* ctx, int32_t split_den);
+
 /* Kernel timing with HIP events for every kernel of the GBR_K_* kinds whose
  * bit (1 << kind) is set in kinds_mask (0 disables; eager launches only:
  * md_step does not replay graphs while any kind is timed).  The pair kernels'

@@ -27,7 +27,7 @@ K_BORN_PAIR, K_ENERGY_PAIR, K_CHAIN_PAIR, K_PER_ATOM, K_TITRATION, K_EXCHANGE, K
 KERNEL_KINDS = ("born_pair", "energy_pair", "chain_pair", "per_atom", "titration", "exchange")
 
 EXPORTED = ("gbr_ctx_create", "gbr_ctx_destroy", "gbr_check", "gbr_last_error", "gbr_ctx_sizes",
-            "gbr_set_launch", "gbr_set_blocking", "gbr_set_timing", "gbr_get_timing",
+            "gbr_set_launch", "gbr_set_blocking", "gbr_set_split", "gbr_set_timing", "gbr_get_timing",
             "gb_born_radii", "gb_energy_forces", "titration_delta_e", "remd_exchange", "md_step",
             "gbr_fx_to_float", "gbr_energies", "gbr_exchange_inputs", "gb_born_radii_noalloc")
 
@@ -88,6 +88,7 @@ def _load():
     L.gbr_ctx_sizes.argtypes = [_vp, P(i32), P(i32), P(i64)]
     L.gbr_set_launch.argtypes = [_vp, i32, i32]
     L.gbr_set_blocking.argtypes = [_vp, i32, i32, i32]
+    L.gbr_set_split.argtypes = [_vp, i32]
     L.gbr_set_timing.argtypes = [_vp, i32]
     L.gbr_get_timing.argtypes = [_vp, P(C.c_double), P(i64)]
     L.gb_born_radii.argtypes = [_vp] + [_vp] * 6 + [_vp]

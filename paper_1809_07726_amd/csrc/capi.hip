@@ -268,6 +268,68 @@ uint64_t hash_args(const MDArgs& a) {
     return f.h | 1ull;
 }
 
+// The pair work list of blocking index k (NI = 1, 2, 4, 8) at the context's
+// split level, and with both cutoffs its packed parts; frees what an earlier
+// build left.  The packed-list buffers (tile boxes, counters) must exist.
+void free_list(gbr::PairList& L) {
+    (void)hipFree(L.items); (void)hipFree(L.iblk); (void)hipFree(L.blk_p0); (void)hipFree(L.win);
+    (void)hipFree(L.blk_win);
+    L.items = nullptr; L.iblk = nullptr; L.blk_p0 = nullptr; L.win = nullptr; L.blk_win = nullptr;
+    for (int v = 0; v < 2; ++v) {
+        (void)hipFree(L.run[v]); (void)hipFree(L.blk_count[v]); (void)hipFree(L.pk_hdr[v]);
+        (void)hipFree(L.pk_j[v]);
+        L.run[v] = nullptr; L.blk_count[v] = nullptr; L.pk_hdr[v] = nullptr; L.pk_j[v] = nullptr;
+    }
+}
+
+int build_list(gbr_ctx* c, int k) {
+    static const int nis[4] = {1, 2, 4, 8};
+    static_assert(sizeof(gbr::PairItem) == sizeof(int2), "item layout");
+    static_assert(sizeof(gbr::PackWindow) == sizeof(int4), "window layout");
+    gbr::PairList& L = c->lists[k];
+    free_list(L);
+    const int32_t n_rep = c->n_rep;
+    std::vector<gbr::PairItem> items;
+    gbr::build_pair_items(c->h_atom_off.data(), n_rep, nis[k], items, c->split_den);
+    if (items.size() > 0x7FFFFFFF) return fail(GBR_E_INVAL, "work list too long");
+    int rc = GBR_OK;
+    L.ni = nis[k];
+    L.n_items = (int32_t)items.size();
+    if ((rc = dev_alloc(&L.items, items.size()))) return rc;
+    if (!items.empty() && (rc = upload(L.items, items.data(), sizeof(int2) * items.size()))) return rc;
+    if (!c->packed) return GBR_OK;
+    std::vector<gbr::PairItem> intra, iblocks;
+    std::vector<int32_t> p0, blk_win;
+    std::vector<gbr::PackWindow> wins;
+    int64_t cap = 0;
+    gbr::build_packed_parts(c->h_atom_off.data(), n_rep, nis[k], items, intra, iblocks, p0, wins, blk_win, cap);
+    if ((int64_t)intra.size() + cap > 0x7FFFFFFF || cap * 64 > 0x7FFFFFFF)
+        return fail(GBR_E_INVAL, "work list too long");
+    L.n_intra = (int32_t)intra.size();
+    L.n_iblk = (int32_t)iblocks.size();
+    L.n_win = (int32_t)wins.size();
+    L.pk_cap = cap;
+    if ((rc = dev_alloc(&L.iblk, iblocks.size()))) return rc;
+    if (!iblocks.empty() && (rc = upload(L.iblk, iblocks.data(), sizeof(int2) * iblocks.size()))) return rc;
+    if ((rc = dev_alloc(&L.blk_p0, p0.size()))) return rc;
+    if (!p0.empty() && (rc = upload(L.blk_p0, p0.data(), sizeof(int32_t) * p0.size()))) return rc;
+    if ((rc = dev_alloc(&L.win, wins.size()))) return rc;
+    if (!wins.empty() && (rc = upload(L.win, wins.data(), sizeof(int4) * wins.size()))) return rc;
+    if ((rc = dev_alloc(&L.blk_win, blk_win.size()))) return rc;
+    if ((rc = upload(L.blk_win, blk_win.data(), sizeof(int32_t) * blk_win.size()))) return rc;
+    for (int v = 0; v < 2; ++v) {
+        if ((rc = dev_alloc(&L.blk_count[v], iblocks.size()))) return rc;
+        if (hipMemset(L.blk_count[v], 0, sizeof(int32_t) * std::max<size_t>(iblocks.size(), 1)) != hipSuccess)
+            return fail(GBR_E_HIP, "clearing the packing counts");
+        if ((rc = dev_alloc(&L.run[v], (size_t)(L.n_intra + cap)))) return rc;
+        if (!intra.empty() && (rc = upload(L.run[v], intra.data(), sizeof(int2) * intra.size()))) return rc;
+        if ((rc = dev_alloc(&L.pk_hdr[v], std::max<size_t>((size_t)cap, 1)))) return rc;
+        if ((rc = dev_alloc(&L.pk_j[v], std::max<size_t>((size_t)cap * 64, 1)))) return rc;
+        L.n_run[v] = c->pack_count + 2 * k + v;
+    }
+    return GBR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -334,19 +396,6 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     c->n_tiles = (int32_t)tl.size();
     if ((rc = dev_alloc(&c->tiles, tl.size()))) return done(rc);
     if ((rc = upload(c->tiles, tl.data(), sizeof(int2) * tl.size()))) return done(rc);
-    const int nis[4] = {1, 2, 4, 8};
-    std::vector<gbr::PairItem> items;
-    static_assert(sizeof(gbr::PairItem) == sizeof(int2), "item layout");
-    for (int k = 0; k < 4; ++k) {
-        gbr::build_pair_items(c->h_atom_off.data(), n_rep, nis[k], items);
-        if (items.size() > 0x7FFFFFFF) return done(fail(GBR_E_INVAL, "work list too long"));
-        c->lists[k].ni = nis[k];
-        c->lists[k].n_items = (int32_t)items.size();
-        if ((rc = dev_alloc(&c->lists[k].items, items.size()))) return done(rc);
-        if (!items.empty() &&
-            (rc = upload(c->lists[k].items, items.data(), sizeof(int2) * items.size())))
-            return done(rc);
-    }
     // with both cutoffs the pair passes run packed lists
     c->packed = p.cut > 0 && p.rgbmax > 0;
     if (c->packed) {
@@ -359,45 +408,9 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
         if ((rc = upload(c->tile_base, tb.data(), sizeof(int32_t) * n_rep))) return done(rc);
         if ((rc = dev_alloc(&c->tile_box, 2 * (size_t)c->n_tiles))) return done(rc);
         if ((rc = dev_alloc(&c->pack_count, 8))) return done(rc);
-        std::vector<gbr::PairItem> intra, iblocks;
-        std::vector<int32_t> p0;
-        std::vector<gbr::PackWindow> wins;
-        std::vector<int32_t> blk_win;
-        static_assert(sizeof(gbr::PackWindow) == sizeof(int4), "window layout");
-        for (int k = 0; k < 4; ++k) {
-            gbr::PairList& L = c->lists[k];
-            gbr::build_pair_items(c->h_atom_off.data(), n_rep, nis[k], items);
-            int64_t cap = 0;
-            gbr::build_packed_parts(c->h_atom_off.data(), n_rep, nis[k], items, intra, iblocks, p0, wins, blk_win,
-                                    cap);
-            if ((int64_t)intra.size() + cap > 0x7FFFFFFF || cap * 64 > 0x7FFFFFFF)
-                return done(fail(GBR_E_INVAL, "work list too long"));
-            L.n_intra = (int32_t)intra.size();
-            L.n_iblk = (int32_t)iblocks.size();
-            L.n_win = (int32_t)wins.size();
-            L.pk_cap = cap;
-            if ((rc = dev_alloc(&L.iblk, iblocks.size()))) return done(rc);
-            if (!iblocks.empty() && (rc = upload(L.iblk, iblocks.data(), sizeof(int2) * iblocks.size())))
-                return done(rc);
-            if ((rc = dev_alloc(&L.blk_p0, p0.size()))) return done(rc);
-            if (!p0.empty() && (rc = upload(L.blk_p0, p0.data(), sizeof(int32_t) * p0.size()))) return done(rc);
-            if ((rc = dev_alloc(&L.win, wins.size()))) return done(rc);
-            if (!wins.empty() && (rc = upload(L.win, wins.data(), sizeof(int4) * wins.size()))) return done(rc);
-            if ((rc = dev_alloc(&L.blk_win, blk_win.size()))) return done(rc);
-            if ((rc = upload(L.blk_win, blk_win.data(), sizeof(int32_t) * blk_win.size()))) return done(rc);
-            for (int v = 0; v < 2; ++v) {
-                if ((rc = dev_alloc(&L.blk_count[v], iblocks.size()))) return done(rc);
-                if (hipMemset(L.blk_count[v], 0, sizeof(int32_t) * std::max<size_t>(iblocks.size(), 1)) != hipSuccess)
-                    return done(fail(GBR_E_HIP, "clearing the packing counts"));
-                if ((rc = dev_alloc(&L.run[v], (size_t)(L.n_intra + cap)))) return done(rc);
-                if (!intra.empty() && (rc = upload(L.run[v], intra.data(), sizeof(int2) * intra.size())))
-                    return done(rc);
-                if ((rc = dev_alloc(&L.pk_hdr[v], std::max<size_t>((size_t)cap, 1)))) return done(rc);
-                if ((rc = dev_alloc(&L.pk_j[v], std::max<size_t>((size_t)cap * 64, 1)))) return done(rc);
-                L.n_run[v] = c->pack_count + 2 * k + v;
-            }
-        }
     }
+    for (int k = 0; k < 4; ++k)
+        if ((rc = build_list(c, k))) return done(rc);
     // default register blocking: more i atoms per lane for larger replicas
     const int ni = max_n >= 4096 ? 8 : (max_n >= 512 ? 4 : (max_n >= 128 ? 2 : 1));
     c->ni_born = c->ni_energy = c->ni_chain = ni;
@@ -440,13 +453,7 @@ int gbr_ctx_destroy(gbr_ctx* c) {
     for (auto& ev : c->timer.pool) if (ev) (void)hipEventDestroy(ev);
     (void)hipFree(c->atom_off);
     (void)hipFree(c->tiles);
-    for (auto& L : c->lists) {
-        (void)hipFree(L.items); (void)hipFree(L.iblk); (void)hipFree(L.blk_p0); (void)hipFree(L.win); (void)hipFree(L.blk_win);
-        for (int v = 0; v < 2; ++v) {
-            (void)hipFree(L.run[v]); (void)hipFree(L.blk_count[v]); (void)hipFree(L.pk_hdr[v]);
-            (void)hipFree(L.pk_j[v]);
-        }
-    }
+    for (auto& L : c->lists) free_list(L);
     (void)hipFree(c->tile_base);
     (void)hipFree(c->tile_box);
     (void)hipFree(c->pack_count);
@@ -486,6 +493,18 @@ int gbr_set_blocking(gbr_ctx* c, int32_t ni_born, int32_t ni_energy, int32_t ni_
     if (!ok(ni_born) || !ok(ni_energy) || !ok(ni_chain))
         return fail(GBR_E_INVAL, "i atoms per lane must be 1, 2, 4 or 8");
     c->ni_born = ni_born; c->ni_energy = ni_energy; c->ni_chain = ni_chain;
+    for (auto& g : c->graph) if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    return GBR_OK;
+}
+
+int gbr_set_split(gbr_ctx* c, int32_t split_den) {
+    if (int rc = check_ctx(c)) return rc;
+    if (split_den < 1 || split_den > 1024) return fail(GBR_E_INVAL, "split_den must be 1..1024");
+    if (split_den == c->split_den) return GBR_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(GBR_E_HIP, "synchronizing before the list rebuild");
+    c->split_den = split_den;
+    for (int k = 0; k < 4; ++k)
+        if (int rc = build_list(c, k)) return rc;
     for (auto& g : c->graph) if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     return GBR_OK;
 }

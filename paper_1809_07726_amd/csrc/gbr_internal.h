@@ -75,6 +75,7 @@ struct gbr_ctx {
     float4* tile_box = nullptr;      // [2 n_tiles] per-tile bounding boxes (min, max)
     int32_t* pack_count = nullptr;   // [8] items per list and radius
     int ni_born = 4, ni_energy = 4, ni_chain = 4;
+    int split_den = 16;              // the last ceil(nb / split_den) block items of a replica run as halves
     gbr::LaunchShape shape;
     // workspace
     int64_t* psi_fx = nullptr;       // [N] sum_j h_ij (2^40)

@@ -53,7 +53,6 @@ struct PairExt {
 
 namespace {
 
-constexpr int MAXW = 4;                 // wavefronts per workgroup
 constexpr float FAR_R2 = 1.0e30f;       // r^2 used for masked pairs
 constexpr float LOG2E = 1.4426950408889634f;
 

@@ -21,11 +21,12 @@
 //                 triangles of a and of b, phase 1 = the cross pairs a x b,
 //                 rotation steps 0..31 and 32..63 side by side.  Phase 1 exists
 //                 only if tile b does.
-// The last ceil(nb / SPLIT_DEN) block items of each replica's nb (in the order
-// below) run as two halves each: rotation steps 0..31 and 32..63, the j
-// accumulators of the first half ending on lane (l + 32) mod 64, those of the
-// second back on lane l.  The choice depends on the replica alone, so a
-// replica's results do not depend on the rest of the batch.
+// The last ceil(nb / split_den) block items of each replica's nb (in the order
+// below; split_den = SPLIT_DEN unless the caller sets the split level) run as
+// two halves each: rotation steps 0..31 and 32..63, the j accumulators of the
+// first half ending on lane (l + 32) mod 64, those of the second back on lane
+// l.  The choice depends on the replica and the split level alone, so at one
+// split level a replica's results do not depend on the rest of the batch.
 // Encoding: x = rep | (half << 26) | (type << 30), half = 0 (whole), 1, 2;
 // y = (A << 16) | B (A = IB for blocks).
 #pragma once
@@ -54,7 +55,8 @@ inline PairItem make_item(int32_t rep, int32_t type, int32_t a, int32_t b, int32
 
 // Items of every replica, within a replica I block by I block; then each
 // eighth of the list reordered (below).
-inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vector<PairItem>& out) {
+inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vector<PairItem>& out,
+                             int32_t split_den = SPLIT_DEN) {
     out.clear();
     std::vector<uint32_t> rank;                 // position of each item within its replica
     std::vector<PairItem> one;
@@ -77,7 +79,7 @@ inline void build_pair_items(const int32_t* off, int32_t n_rep, int ni, std::vec
         }
         size_t nb = 0;
         for (const PairItem& it : one) nb += ((uint32_t)it.x >> 30) == (uint32_t)ITEM_BLOCK;
-        size_t split = (nb + SPLIT_DEN - 1) / SPLIT_DEN;    // block items still to split, from the end
+        size_t split = (nb + split_den - 1) / split_den;    // block items still to split, from the end
         for (size_t k = one.size(); k-- > 0 && split > 0;) {
             if (((uint32_t)one[k].x >> 30) != (uint32_t)ITEM_BLOCK) continue;
             one[k].x |= 1 << 26;

@@ -55,6 +55,9 @@ class Context:
     def set_blocking(self, ni_born, ni_energy, ni_chain):
         check(A.lib.gbr_set_blocking(self.h, ni_born, ni_energy, ni_chain))
 
+    def set_split(self, split_den=16):
+        check(A.lib.gbr_set_split(self.h, split_den))
+
     def set_timing(self, on, kinds=None):
         """Time kernels with HIP events: all kinds when on is True, or only the
         named kinds (see _capi.KERNEL_KINDS)."""

@@ -1,12 +1,15 @@
 """Autotuner for the pair kernels.
 
 Times the three pair passes (descreening, energy, chain rule) on the caller's
-own batch for every register blocking (i atoms per lane: 1, 2, 4, 8) and a set
+own batch for every register blocking (i atoms per lane: 1, 2, 4, 8), a set
 of launch shapes (wavefronts per workgroup x workgroups per CU of the
-persistent grid), using the library's HIP-event kernel timers after a short
-warm-up (device clocks ramp up under sustained load), and installs
-the fastest combination in the context: per pass the fastest blocking, and the
-launch shape whose summed pass time is lowest.  Results can be cached in a JSON
+persistent grid) and two split levels of the work list (the last sixteenth of
+each replica's block items as half items, or all of them: more, shorter items
+for batches too small to fill the chip), using the library's HIP-event kernel
+timers after a short warm-up (device clocks ramp up under sustained load), and
+installs the fastest combination in the context: per pass the fastest
+blocking, and the split level and launch shape whose summed pass time is
+lowest.  Results can be cached in a JSON
 file keyed by the device architecture and the batch's replica sizes.
 """
 from __future__ import annotations
@@ -21,6 +24,7 @@ import torch
 PASSES = ("born_pair", "energy_pair", "chain_pair")
 SHAPES = ((4, 8), (4, 16), (4, 32), (2, 16))
 BLOCKINGS = (1, 2, 4, 8)
+SPLITS = (16, 1)
 
 
 def batch_key(ctx) -> str:
@@ -57,43 +61,48 @@ def _warm(ctx, t, ms=50.0):
         torch.cuda.synchronize()
 
 
-def autotune(ctx, t: dict, reps: int = 10, shapes=SHAPES, blockings=BLOCKINGS,
+def autotune(ctx, t: dict, reps: int = 10, shapes=SHAPES, blockings=BLOCKINGS, splits=SPLITS,
              cache: str | None = None) -> dict:
     """Tune ctx for the inputs in t (the DeviceBatch tensors); returns
     {"shape": (wpg, gpc), "blocking": (ni_born, ni_energy, ni_chain),
-     "ms": {pass: ms}, "table": [...]}."""
+     "split": split_den, "ms": {pass: ms}, "table": [...]}."""
     key = batch_key(ctx)
     if cache and os.path.exists(cache):
         store = json.load(open(cache))
         if key in store:
             best = store[key]
+            ctx.set_split(best.get("split", 16))
             ctx.set_launch(*best["shape"])
             ctx.set_blocking(*best["blocking"])
             best["cached"] = True
             return best
     _warm(ctx, t)
     table = []
-    for shape in shapes:
-        ctx.set_launch(*shape)
-        for ni in blockings:
-            ctx.set_blocking(ni, ni, ni)
-            ms = _time_eval(ctx, t, reps)
-            table.append({"shape": list(shape), "ni": ni, **ms})
+    for split in splits:
+        ctx.set_split(split)
+        for shape in shapes:
+            ctx.set_launch(*shape)
+            for ni in blockings:
+                ctx.set_blocking(ni, ni, ni)
+                ms = _time_eval(ctx, t, reps)
+                table.append({"split": split, "shape": list(shape), "ni": ni, **ms})
     best = None
-    for shape in shapes:
-        rows = [r for r in table if tuple(r["shape"]) == tuple(shape)]
-        pick = {p: min(rows, key=lambda r: r[p]) for p in PASSES}
-        total = sum(pick[p][p] for p in PASSES)
-        if best is None or total < best["total_ms"]:
-            best = {"shape": list(shape), "blocking": [pick[p]["ni"] for p in PASSES],
-                    "ms": {p: pick[p][p] for p in PASSES}, "total_ms": total}
+    for split in splits:
+        for shape in shapes:
+            rows = [r for r in table if tuple(r["shape"]) == tuple(shape) and r["split"] == split]
+            pick = {p: min(rows, key=lambda r: r[p]) for p in PASSES}
+            total = sum(pick[p][p] for p in PASSES)
+            if best is None or total < best["total_ms"]:
+                best = {"split": split, "shape": list(shape), "blocking": [pick[p]["ni"] for p in PASSES],
+                        "ms": {p: pick[p][p] for p in PASSES}, "total_ms": total}
+    ctx.set_split(best["split"])
     ctx.set_launch(*best["shape"])
     ctx.set_blocking(*best["blocking"])
     best["table"] = table
     best["key"] = key
     if cache:
         store = json.load(open(cache)) if os.path.exists(cache) else {}
-        store[key] = {k: best[k] for k in ("shape", "blocking", "ms", "total_ms")}
+        store[key] = {k: best[k] for k in ("split", "shape", "blocking", "ms", "total_ms")}
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         with open(cache, "w") as fh:
             json.dump(store, fh, indent=1)
