@@ -36,10 +36,12 @@ def soa_to_aos(x, n):
     return np.asarray(x, dtype=np.float64).reshape(3, n).T
 
 
-def gpu_eval(b, grad_q=False, grad_rho=False, blocking=None, launch=None, params=None):
+def gpu_eval(b, grad_q=False, grad_rho=False, blocking=None, launch=None, params=None, split=None):
     """Born radii, energies and gradients of every replica on the GPU."""
     from paper_1809_07726_amd.gb import Context
     ctx = Context(b["atom_off"], params)
+    if split:
+        ctx.set_split(split)
     if blocking:
         ctx.set_blocking(*blocking)
     if launch:

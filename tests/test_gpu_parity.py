@@ -60,6 +60,18 @@ def test_every_register_blocking(ni):
     _check(b, gpu_eval(b, True, True, blocking=(ni, ni, ni)), _oracle_batch(b), grads=True)
 
 
+@pytest.mark.parametrize("ni", [1, 2, 4])
+def test_every_block_item_halved_matches_oracle(ni):
+    """Split level 1 (every block item run as two halves) on ragged replicas,
+    with the radius and charge gradients, against the oracle."""
+    sizes = [1, 37, 64, 65, 300, 700, 1300]
+    systems = [synth.draw_system(n, 600 + n, 1 if n >= 16 else 0, 1 if n >= 16 else 0) for n in sizes]
+    b = synth.assemble(systems, 1, (-0.2,), (7.0,), (300.0,), (0,))
+    # items hold their partials in FP32 until their flush, so halving changes
+    # the rounding, not the sum: held to the oracle, not to the default level
+    _check(b, gpu_eval(b, True, True, blocking=(ni, ni, ni), split=1), _oracle_batch(b), grads=True)
+
+
 @pytest.mark.parametrize("ni", [1, 2])
 def test_launch_shapes_are_bitwise_identical(ni):
     """One wavefront per workgroup or four, few or many workgroups per CU: each

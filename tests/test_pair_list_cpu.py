@@ -20,11 +20,12 @@ HARNESS = r"""
 #include <cstdlib>
 #include "pair_list.h"
 int main(int argc, char** argv) {
-    const int ni = std::atoi(argv[1]);
+    const int ni = std::atoi(argv[1]);                  // negative: split level 1 (every block item halved)
     std::vector<int32_t> off{0};
     for (int k = 2; k < argc; ++k) off.push_back(off.back() + std::atoi(argv[k]));
     std::vector<gbr::PairItem> items;
-    gbr::build_pair_items(off.data(), (int32_t)off.size() - 1, ni, items);
+    gbr::build_pair_items(off.data(), (int32_t)off.size() - 1, ni < 0 ? -ni : ni, items,
+                          ni < 0 ? 1 : gbr::SPLIT_DEN);
     for (const auto& it : items)
         std::printf("%d %d %d %d %d\n", it.x & 0x3FFFFFF, (int)((unsigned)it.x >> 30), it.y >> 16,
                     it.y & 0xFFFF, (it.x >> 26) & 3);
@@ -42,19 +43,19 @@ def harness(tmp_path_factory):
     return str(exe)
 
 
-def _items(exe, ni, sizes):
+def _items(exe, ni, sizes, split_den=16):
     """Rows (replica, type, A, B, half)."""
-    out = subprocess.check_output([exe, str(ni)] + [str(s) for s in sizes], text=True)
+    out = subprocess.check_output([exe, str(ni if split_den == 16 else -ni)] + [str(s) for s in sizes], text=True)
     return np.array([list(map(int, l.split())) for l in out.splitlines()], dtype=np.int64).reshape(-1, 5)
 
 
 SPLIT_DEN = 16      # the last ceil(nb / 16) block items of a replica run as halves
 
 
-def _natural_items(ni, n):
+def _natural_items(ni, n, split_den=SPLIT_DEN):
     """(type, A, B, half) of one replica's items in their order within the
     replica: I block by I block, its triangle or diagonal items, then its block
-    items; the last ceil(nb / 16) block items as two halves each."""
+    items; the last ceil(nb / split_den) block items as two halves each."""
     T, B = (n + 63) // 64, (n + 64 * ni - 1) // (64 * ni)
     out = []
     for ib in range(B):
@@ -69,7 +70,7 @@ def _natural_items(ni, n):
             j0 = 2 * ib + 2
         out += [(0, ib, j) for j in range(j0, T)]
     blocks = [k for k, it in enumerate(out) if it[0] == 0]
-    split = set(blocks[len(blocks) - (len(blocks) + SPLIT_DEN - 1) // SPLIT_DEN:])
+    split = set(blocks[len(blocks) - (len(blocks) + split_den - 1) // split_den:])
     res = []
     for k, it in enumerate(out):
         res += [(*it, 1), (*it, 2)] if k in split else [(*it, 0)]
@@ -125,15 +126,17 @@ def _pairs_of_item(n, ni, typ, A, B, half):
     return np.concatenate(out)
 
 
+@pytest.mark.parametrize("split_den", [16, 1])
 @pytest.mark.parametrize("ni", [1, 2, 4, 8])
-def test_every_pair_exactly_once(harness, ni):
+def test_every_pair_exactly_once(harness, ni, split_den):
+    """At the default split level and with every block item halved."""
     sizes = [1, 2, 63, 64, 65, 127, 128, 129, 200, 511, 640, 1000, 3000]
-    items = _items(harness, ni, sizes)
+    items = _items(harness, ni, sizes, split_den)
     # each eighth of the list (one XCD's share): 64-step block items first, then
     # the 32-step triangle and diagonal items; within each group the replicas
     # interleaved: items by their position within their replica, then replica
     N = len(items)
-    natural = [_natural_items(ni, n) for n in sizes]
+    natural = [_natural_items(ni, n, split_den) for n in sizes]
     assert sorted(map(tuple, items.tolist())) == sorted(
         (r, *it) for r, its in enumerate(natural) for it in its)
     # rank: position of the (whole) item within its replica, halves sharing it
