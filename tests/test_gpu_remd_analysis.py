@@ -9,6 +9,7 @@ import torch
 
 import oracle
 from common import coupled_sites_system, four_state_constants, four_state_energies
+from gpu_common import note
 from paper_1809_07726_amd import analysis as A
 
 pytestmark = pytest.mark.gpu
@@ -61,7 +62,10 @@ def test_e_ph_t_remd_walks_acceptance_and_titration_fits():
 
     # f1: every replica of every instance walks the whole 5 x 5 x 2 grid
     ws = A.walk_summary(A.residence_histogram(tg, 5, 5, len(TS)))
-    assert ws["fraction_visited_all"] == 1.0 and ws["worst_ratio"] < 10.0, ws["worst_ratio"]
+    note("residence max/min, worst replica", ws["worst_ratio"])
+    note("residence max/min, median replica", np.median(ws["max_min_ratio"]))
+    # 4,000 snapshots over 50 points: the worst of 400 replicas measured 3.8
+    assert ws["fraction_visited_all"] == 1.0 and ws["worst_ratio"] < 5.0, ws["worst_ratio"]
     # every replica stays on a permutation of its instance's grid
     G = 5 * 5 * len(TS)
     gi = A.grid_index(tg, 5, len(TS)).reshape(n_snap, n_inst, G)
@@ -93,3 +97,63 @@ def test_e_ph_t_remd_walks_acceptance_and_titration_fits():
             p_fit, hill = A.fit_pka(pHs, fH[ie, :, iT])
             p_pred = float(A.eq8_sum_pka(E, k["E0_prot"], k["E0_deprot"], k["pKa_red"], T))
             assert abs(p_fit - p_pred) < 0.12 and abs(hill - 1) < 0.1, (T, E, p_fit, p_pred, hill)
+
+
+def test_fig7_analogue_every_replica_visits_every_e_t_ph_combination():
+    """The walk check of the paper's Fig. 7 on a grid of the 192-replica
+    E,T,pH shape: 8 redox potentials 30 mV apart, 4 temperatures 20 K apart and
+    6 pH values 0.5 apart (the paper's spacings), one instance of the frozen
+    coupled-site model.  Every replica must visit all 192 combinations; the
+    most to least visited ratio per replica and the acceptance per dimension
+    are recorded, and the acceptances are held to the oracle's on the same
+    grid."""
+    from paper_1809_07726_amd.gb import MD, Context, DeviceBatch
+    b0 = coupled_sites_system()
+    k = four_state_constants(four_state_energies(b0), 300.0, b0["ref_value"][0], b0["ref_value"][1])
+    pc = 0.5 * (k["pKa_oxi"] + k["pKa_red"])
+    pHs = tuple(np.round(pc + 0.5 * (np.arange(6) - 2.5), 3))
+    e_mid = float(A.eq7_e0(np.mean(pHs), k["E0_prot"], [k["pKa_red"]], [k["pKa_oxi"]], 300.0))
+    Es = tuple(np.round(e_mid + 0.03 * (np.arange(8) - 3.5), 4))
+    Ts = (280.0, 300.0, 320.0, 340.0)
+    nE, npH, nT = len(Es), len(pHs), len(Ts)
+    G = nE * npH * nT
+    b = coupled_sites_system(pH_vals=pHs, E_vals=Es, T_vals=Ts, n_inst=1)
+    ctx = Context(b["atom_off"])
+    d = DeviceBatch.from_numpy(b)
+    md = MD(ctx, d, b, seed=777)
+    md.run(0, init_forces=True)
+    n_chunks, chunk, every = 12, 4000, 2
+    mult = torch.tensor([npH * nT, nT, 1, 0], dtype=torch.int64, device="cuda")
+    rep = torch.arange(G, dtype=torch.int64, device="cuda") * G
+    counts = torch.zeros(G * G, dtype=torch.int64, device="cuda")
+    buf = torch.empty((chunk,) + d.t["target_idx"].shape, dtype=d.t["target_idx"].dtype, device="cuda")
+    ratios = []
+    for c in range(n_chunks):
+        for i in range(chunk):
+            md.run(every)
+            buf[i].copy_(d.t["target_idx"])
+        g = (buf.view(chunk, G, 4).long() * mult).sum(-1) + rep
+        counts += torch.bincount(g.reshape(-1), minlength=G * G)
+        ratios.append(A.walk_summary(counts.view(G, G).cpu().numpy())["worst_ratio"])
+    torch.cuda.synchronize()
+    ctx.check()
+    ws = A.walk_summary(counts.view(G, G).cpu().numpy())
+    r = A.exchange_acceptance(md.ex_stats.cpu().numpy(), 1, nE, npH, nT)
+    ctx.close()
+    for n, rt in zip((chunk * (c + 1) for c in range(n_chunks)), ratios):
+        note(f"Fig. 7 grid: worst max/min after {n:>5} exchanges", rt)
+    note("Fig. 7 grid: max/min, median replica", np.median(ws["max_min_ratio"]))
+    for dim in ("E", "pH", "T"):
+        note(f"Fig. 7 grid: {dim} acceptance", r[dim]["rate"])
+    assert ws["fraction_visited_all"] == 1.0
+    # the paper reports at most 2.2 for the replicas it shows; 48,000 attempts
+    # bring every one of the 192 replicas below that (1.92 measured)
+    assert ws["worst_ratio"] < 2.2, ws["worst_ratio"]
+
+    bo = coupled_sites_system(pH_vals=pHs, E_vals=Es, T_vals=Ts, n_inst=1)
+    cfg, st, arr, keep = oracle.make_md(bo, seed=99)
+    oracle.md_run(cfg, st, 0, 0, True)
+    oracle.md_run(cfg, st, 0, 1000, False)
+    ro = A.exchange_acceptance(np.concatenate([arr["ex_att"], arr["ex_acc"]]), 1, nE, npH, nT)
+    for dim in ("E", "pH", "T"):
+        assert abs(r[dim]["rate"] - ro[dim]["rate"]) < 0.02, (dim, r[dim]["rate"], ro[dim]["rate"])
