@@ -101,6 +101,8 @@ extern "C" {
 
 typedef struct gbr_ctx gbr_ctx;
 
+#define GBR_MAX_ATOMS (1 << 28)   /* atoms of one batch (gbr_ctx_create) */
+
 /* Generalized Born model constants.  OBC-II (igb=2): k_e = 332.0522173,
  * eps_in = 1, eps_out = 78.5, offset = 0.09 A, (alpha, beta, gamma) =
  * (1.0, 0.8, 4.85).  Optional (0 = off, the paper's setting):
@@ -164,16 +166,19 @@ typedef struct {
 
 /* Create a context for one batch layout on the current HIP device.
  * atom_off_host: HOST array [n_rep+1], atom_off[0] = 0, non-decreasing, every
- * replica with at least 1 atom; 1 <= n_rep < 2^26.  Allocates the workspace (a few int64/float per
- * atom, 4 KiB per replica for the energy pass's partial sums, the pair work
- * lists; with both cutoffs set also the packed lists,
- * up to 2 x 256 bytes per later tile of every I block and blocking, which the
- * pair passes rebuild from the positions at every evaluation).  Errors:
+ * replica with at least 1 and at most 64 x 65535 atoms; 1 <= n_rep < 2^26;
+ * at most GBR_MAX_ATOMS atoms in all (3 x n_atoms indexes fit int32).
+ * Allocates the workspace (a few int64/float per atom, 4 KiB per replica
+ * for the energy pass's partial sums, the pair work lists; with both cutoffs
+ * set also the packed lists, up to 2 x 256 bytes per later tile of every I
+ * block and blocking, which the pair passes rebuild from the positions at
+ * every evaluation).  Errors:
  * GBR_E_INVAL, GBR_E_NODEVICE, GBR_E_NOMEM, GBR_E_HIP. */
 int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
                    const int32_t* atom_off_host);
 
-/* Synchronize the device and release everything the context owns. */
+/* Synchronize the device and release everything the context owns; a null
+ * ctx is a no-op that returns GBR_OK. */
 int gbr_ctx_destroy(gbr_ctx* ctx);
 
 /* Read (and clear) the device error word after synchronizing `stream`.

@@ -21,7 +21,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gbr_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# GBR_ORACLE_LIB names another build of gbr_oracle.c to load (the sanitized
+# build that the CPU sanitizer test makes); unset, the in-tree library
+_LIB = os.environ.get("GBR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 
 def build(force: bool = True) -> str:

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgbremd.so")
 GBR_OK, GBR_E_INVAL, GBR_E_HIP, GBR_E_NOMEM, GBR_E_NODEVICE, GBR_E_NUMERIC = 0, -1, -2, -3, -4, -5
 ERR_NONFINITE, ERR_OVERFLOW, ERR_RADIUS, ERR_SITE, ERR_LAYOUT = 1, 2, 4, 8, 16
 NOALLOC_MAX_ATOMS = 1 << 20
+MAX_ATOMS = 1 << 28             # GBR_MAX_ATOMS: atoms of one batch
 FX_BITS_FORCE, FX_BITS_ENERGY = 40, 32
 GRAD_Q, GRAD_RHO, ZERO_OUT = 1, 2, 4
 MD_INIT_FORCES, MD_GRAPH = 1, 2

@@ -347,12 +347,15 @@ int gbr_ctx_create(gbr_ctx** out, const gbr_gb_params* params, int32_t n_rep,
     int64_t pairs = 0;
     int32_t max_n = 0;
     for (int r = 0; r < n_rep; ++r) {
-        const int n = atom_off_host[r + 1] - atom_off_host[r];
-        if (n < 1) return fail(GBR_E_INVAL, "replica %d has %d atoms", r, n);
+        // in 64 bits: the difference of two arbitrary int32 offsets can overflow int32
+        const int64_t n = (int64_t)atom_off_host[r + 1] - atom_off_host[r];
+        if (n < 1) return fail(GBR_E_INVAL, "replica %d has %lld atoms", r, (long long)n);
         if (n > 64 * gbr::MAX_TILES) return fail(GBR_E_INVAL, "replica %d too large", r);
-        max_n = std::max(max_n, n);
+        max_n = std::max(max_n, (int32_t)n);
         pairs += (int64_t)n * (n - 1) / 2;
     }
+    if (atom_off_host[n_rep] > GBR_MAX_ATOMS)
+        return fail(GBR_E_INVAL, "%d atoms in the batch; at most %d", atom_off_host[n_rep], GBR_MAX_ATOMS);
     const gbr_gb_params& p = *params;
     if (!(p.k_e > 0) || !(p.eps_in > 0) || !(p.eps_out > 0) || !(p.offset >= 0))
         return fail(GBR_E_INVAL, "GB parameters out of range");

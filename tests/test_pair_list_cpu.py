@@ -14,6 +14,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1809_07726_amd", "csrc")
+# the harnesses run under AddressSanitizer and UndefinedBehaviorSanitizer
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
 
 HARNESS = r"""
 #include <cstdio>
@@ -39,7 +41,7 @@ def harness(tmp_path_factory):
     d = tmp_path_factory.mktemp("pairlist")
     src, exe = d / "h.cpp", d / "h"
     src.write_text(HARNESS)
-    subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)])
+    subprocess.check_call(["g++", "-std=c++17", *SAN, "-I", CSRC, str(src), "-o", str(exe)])
     return str(exe)
 
 
@@ -230,7 +232,7 @@ def pack_harness(tmp_path_factory):
     d = tmp_path_factory.mktemp("packparts")
     src, exe = d / "p.cpp", d / "p"
     src.write_text(PACK_HARNESS)
-    subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)])
+    subprocess.check_call(["g++", "-std=c++17", *SAN, "-I", CSRC, str(src), "-o", str(exe)])
     return str(exe)
 
 
