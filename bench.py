@@ -93,6 +93,11 @@ def traffic_from_profile(kernel, workload):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def tuned_summary(tuned):
+    return {"waves_per_group_x_groups_per_cu": tuned["shape"],
+            "i_atoms_per_lane_born_energy_chain": tuned["blocking"], "split_den": tuned["split"]}
+
+
 def pair_counts(b, cut):
     """Unordered pairs per replica: all of them, or those closer than cut."""
     off = b["atom_off"]
@@ -241,7 +246,8 @@ def main():
             for _ in range(3):
                 y.copy_(x)
             torch.cuda.synchronize()
-        print(json.dumps({"profile_only": True, "steps": K, "ms_per_step": 1000 * dt / K}))
+        print(json.dumps({"profile_only": True, "workload": w.name, "steps": K, "ms_per_step": 1000 * dt / K,
+                          "tuned": tuned_summary(tuned), "source_hash": source_hash()}))
         return
 
     value = K * n_pairs / dt
@@ -361,9 +367,7 @@ def main():
                    "pairs_per_step": n_pairs, "mc_every": w.mc_every,
                    "ex_every": w.ex_every, "graph": bool(args.graph),
                    "accumulation": "int64 fixed point (forces 2^-40, energies 2^-32)",
-                   "tuned": {"waves_per_group_x_groups_per_cu": tuned["shape"],
-                             "i_atoms_per_lane_born_energy_chain": tuned["blocking"],
-                             "split_den": tuned["split"]}},
+                   "tuned": tuned_summary(tuned)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_fp64": err64,
