@@ -395,9 +395,13 @@ __global__ __launch_bounds__(256) void k_energy_pair(
     int64_t* __restrict__ e_stripe, int64_t* __restrict__ dEdq_fx, uint32_t* __restrict__ err)
 {
     constexpr int NSL = NI == 2 ? 2 : 1;
-    extern __shared__ float4 lds_dyn[];          // j tiles: [waves in the group][NSL][2][64]
-    auto lds = reinterpret_cast<float4 (*)[NSL][2][64]>(lds_dyn);
+    // j tiles per wavefront (energy_lds): slot 0 as [2][128], each component's
+    // 64 entries stored twice so that step k reads entry lane + k + 1 without
+    // wrapping; slot 1 (diagonal items' tile b) as [2][64]
+    extern __shared__ float4 lds_dyn[];
     const int lane = threadIdx.x & 63, wv = wave_in_group();
+    float4* const w0 = lds_dyn + wv * (256 + (NSL - 1) * 128);
+    float4* const w1 = w0 + 256;
     const int stride = gridDim.x * (blockDim.x >> 6);
     const float lc = 0.60056120439322491f;       // sqrt(log2(e) / 4)
     const float hl = 0.5f / LOG2E;               // D = D2 / log2(e)
@@ -438,8 +442,14 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         auto fill = [&](int slot, int tb) {
             const int ja = g.a0 + j_fill<EXT>(g, tb, lane);
             const float Rj = Rb[ja];
-            lds[wv][slot][0][lane] = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], q[ja] * sq_ke_in);
-            lds[wv][slot][1][lane] = make_float4(Rj, lc / Rj, 0.5f * sigma[ja], 2.0f * sqrtf(eps[ja]));
+            const float4 v0 = make_float4(xyz[ja], xyz[ntot + ja], xyz[2 * ntot + ja], q[ja] * sq_ke_in);
+            const float4 v1 = make_float4(Rj, lc / Rj, 0.5f * sigma[ja], 2.0f * sqrtf(eps[ja]));
+            if (slot == 0) {
+                w0[lane] = v0; w0[64 + lane] = v0;
+                w0[128 + lane] = v1; w0[192 + lane] = v1;
+            } else {
+                w1[lane] = v0; w1[64 + lane] = v1;
+            }
         };
         fill(0, g.jbase);
         if (NSL > 1 && g.diag && g.phase == 0 && g.u_lim > 1) fill(NSL - 1, g.ibase + 64);
@@ -518,8 +528,9 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         auto kloop = [&](auto full, int k0, int k1) {
             constexpr bool FULL = decltype(full)::value;
             for (int k = k0; k < k1; ++k) {
-                const int m = (lane + k + 1) & 63;
-                const float4 p0 = lds[wv][0][0][m], p1 = lds[wv][0][1][m];
+                const int mu = lane + k + 1;             // 1 .. 127: the second copy past 63
+                const int m = mu & 63;
+                const float4 p0 = w0[mu], p1 = w0[128 + mu];
                 EnergyJ c{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int u = 0; u < NI; ++u)
@@ -530,13 +541,15 @@ __global__ __launch_bounds__(256) void k_energy_pair(
         };
         if constexpr (NI == 2) {
             if (g.diag) {
-                const int s1 = g.phase ? 0 : NSL - 1;
+                // sub-task 1's tile: slot 1 in phase 0, slot 0 in phase 1
+                const float4* const b1 = g.phase ? w0 : w1;
+                const int c1o = g.phase ? 128 : 64;
                 run_diag(g, lane, [&](int m0, int m1, bool ok0, bool ok1) {
                     EnergyJ c0{0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, c1{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                    pair(0, lds[wv][0][0][m0], lds[wv][0][1][m0], ok0, std::false_type{}, c0, true);
+                    pair(0, w0[m0], w0[128 + m0], ok0, std::false_type{}, c0, true);
                     rotate(accj[0], c0);
                     if (g.u_lim > 1) {
-                        pair(1, lds[wv][s1][0][m1], lds[wv][s1][1][m1], ok1, std::false_type{}, c1, true);
+                        pair(1, b1[m1], b1[c1o + m1], ok1, std::false_type{}, c1, true);
                         rotate(accj[NSL - 1], c1);
                     }
                 });
@@ -1028,6 +1041,11 @@ size_t pair_lds(int waves, int ni, int comps) {
     return (size_t)waves * (ni == 2 ? 2 : 1) * comps * 64 * sizeof(float4);
 }
 
+// The energy pass: slot 0 holds its two components twice (2 x 128 float4).
+size_t energy_lds(int waves, int ni) {
+    return (size_t)waves * (256 + (ni == 2 ? 128 : 0)) * sizeof(float4);
+}
+
 // Nothing to launch: the timing events still get recorded (an empty interval).
 hipError_t no_launch(hipStream_t s, const LaunchEvents& ev) {
     if (ev.start) (void)hipEventRecord(ev.start, s);
@@ -1164,7 +1182,7 @@ hipError_t launch_energy_pair(const gbr_ctx* c, const float* xyz, const float* q
     const float taup = (float)((1.0 / c->prm.eps_in - 1.0 / c->prm.eps_out) * c->prm.eps_in);
     const PairExt pe = make_pair_ext(c, L, 1);
 #define GBR_EN(NI, GQ, EX) hipExtLaunchKernelGGL((k_energy_pair<NI, GQ, EX>), grid, block, \
-        pair_lds(c->shape.waves_per_group, NI, 2), s, ev.start, \
+        energy_lds(c->shape.waves_per_group, NI), s, ev.start, \
         ev.stop, 0, items, L.n_items, n_dev, c->atom_off, c->n_atoms, xyz, q, R, sigma, eps, sq, taup, pe, \
         force_fx, c->dEdR_fx, c->e_stripe, dEdq_fx, c->err)
 #define GBR_EN2(NI, GQ) if (uses_ext(c)) GBR_EN(NI, GQ, true); else GBR_EN(NI, GQ, false)
