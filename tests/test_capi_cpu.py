@@ -47,6 +47,14 @@ def test_host_side_argument_checks():
     assert L.gbr_ctx_create(C.byref(h), C.byref(p), 2, bad0) == A.GBR_E_INVAL
     neg = A.obc2(); neg.eps_out = -1.0
     assert L.gbr_ctx_create(C.byref(h), C.byref(neg), 2, off) == A.GBR_E_INVAL
+    # offsets whose difference overflows 32 bits, and a batch over GBR_MAX_ATOMS
+    wide = (C.c_int32 * 3)(0, 5, -2 ** 31)
+    assert L.gbr_ctx_create(C.byref(h), C.byref(p), 2, wide) == A.GBR_E_INVAL
+    nb = A.MAX_ATOMS // 2 ** 20 + 1
+    many = (C.c_int32 * (nb + 1))(*[r << 20 for r in range(nb + 1)])
+    assert L.gbr_ctx_create(C.byref(h), C.byref(p), nb, many) == A.GBR_E_INVAL
+    assert b"at most" in L.gbr_last_error()
+    assert L.gbr_ctx_destroy(None) == A.GBR_OK             # a null context is a no-op
     # every call rejects a null context
     assert L.gb_born_radii(None, None, None, None, None, None, None, None) == A.GBR_E_INVAL
     assert L.gbr_set_launch(None, 4, 8) == A.GBR_E_INVAL
